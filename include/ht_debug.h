@@ -1,0 +1,26 @@
+/*
+ * ht_debug.h -- host-only checks of the launch plans of libht (no GPU used).
+ *
+ * Each function builds the complete launch plan of the corresponding entry
+ * point of ht.h for the given shapes (data pointers in X are ignored: every
+ * buffer is replaced by a fake, disjoint address range of exactly the size the
+ * shapes imply, the workspace by its individual allocations) and proves that
+ * every address any kernel of the plan may read or write lies inside one of
+ * those ranges.  Returns HT_OK, or HT_EINVAL with ht_last_error() naming the
+ * first launch and operand that would leave its buffer.  Meant for tests that
+ * vet new shapes on the CPU before anything runs on a GPU.
+ */
+#ifndef HT_DEBUG_H
+#define HT_DEBUG_H
+#include "ht.h"
+#ifdef __cplusplus
+extern "C" {
+#endif
+ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts);
+ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision);
+ht_status ht_debug_validate_gramians(const ht_desc* X);
+ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m);
+#ifdef __cplusplus
+}
+#endif
+#endif

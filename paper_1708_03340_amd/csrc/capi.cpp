@@ -1,0 +1,1648 @@
+// C ABI of the HT hierarchical-SVD library: argument checks, workspace layout,
+// launch tables and the order of the launches.  Every floating-point step runs
+// in the kernels of gemm.hip, smallla.hip and entries.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ht.h"
+#include "ht_internal.h"
+
+using namespace ht;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static ht_status fail(ht_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HT_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(HT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+// ------------------------------------------------------------------ tree, eq. (balanced)
+namespace ht {
+Tree::Tree(int d_) : d(d_) {
+  nn = 2 * d - 1;
+  parent.assign(nn, -1); son1.assign(nn, -1); son2.assign(nn, -1);
+  lo.assign(nn, 0); hi.assign(nn, 0); depth.assign(nn, 0); height.assign(nn, 0);
+  leaf_node.assign(d, -1);
+  int next = 0;
+  // preorder visit of {mu..nu} (1-based): sons {mu..floor((mu+nu-1)/2)}, rest
+  struct Frame { int mu, nu, par, dep; };
+  std::vector<Frame> stack{{1, d, -1, 0}};
+  std::vector<int> order;
+  while (!stack.empty()) {
+    Frame f = stack.back();
+    stack.pop_back();
+    const int t = next++;
+    lo[t] = f.mu - 1; hi[t] = f.nu - 1; parent[t] = f.par; depth[t] = f.dep;
+    if (f.par >= 0) {
+      if (son1[f.par] < 0) son1[f.par] = t; else son2[f.par] = t;
+    }
+    if (f.mu < f.nu) {
+      const int split = (f.mu + f.nu - 1) / 2;
+      stack.push_back({split + 1, f.nu, t, f.dep + 1});  // second son visited after the first
+      stack.push_back({f.mu, split, t, f.dep + 1});
+    } else {
+      leaf_node[f.mu - 1] = t;
+    }
+  }
+  for (int t = nn - 1; t >= 0; --t)
+    if (son1[t] >= 0) height[t] = 1 + std::max(height[son1[t]], height[son2[t]]);
+}
+int Tree::max_depth() const { return *std::max_element(depth.begin(), depth.end()); }
+}  // namespace ht
+
+// ------------------------------------------------------------------ launch plans
+namespace {
+
+enum OpKind : int {
+  OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH
+};
+
+struct Op {
+  int kind = 0;
+  GemmLaunch g{};            // OP_GEMM (descs = table offset until bound)
+  size_t toff = 0;           // table offset of descriptors / small args
+  int count = 0;
+  void* p0 = nullptr;        // generic pointers
+  void* p1 = nullptr;
+  void* p2 = nullptr;
+  size_t bytes = 0;
+  long long scale0 = 0;
+  int i0 = 0, i1 = 0, i2 = 0, i3 = 0, i4 = 0, i5 = 0;
+  double f0 = 0.0;
+  int64_t c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // OP_COPY sizes and strides
+};
+
+struct Plan {
+  std::vector<Op> ops;
+  std::vector<unsigned char> table;
+  std::vector<unsigned char> key;
+  void* dtable = nullptr;
+  size_t dbytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Appends POD records to the host table image; returns their offset.
+template <typename T>
+size_t put(Plan& P, const std::vector<T>& v) {
+  const size_t off = align256(P.table.size());
+  P.table.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(P.table.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+int esize(int t) { return t == F32 ? 4 : 8; }
+
+// Jacobi scratch: A and V (K^2 each) and one sweep of rotations, (Ke-1) x Ke/2
+// pairs of (c, s) with Ke = K rounded up to even.
+size_t eig_scratch_doubles(int K) {
+  const size_t Ke = (size_t)K + (K & 1);
+  return 2 * (size_t)K * K + (Ke - 1) * Ke;
+}
+
+GemmDesc blank_desc() {
+  GemmDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.KB = 1;
+  d.nbatch = 1;
+  d.alpha = 1.0;
+  return d;
+}
+
+// Adds one GEMM launch over `descs` (all sharing types, math, mode, layouts).
+void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode,
+              bool akc, bool bkc, int target_blocks = 4096) {
+  if (descs.empty()) return;
+  Op op;
+  op.kind = OP_GEMM;
+  int maxtiles = 0, maxbatch = 1, maxkt = 1;
+  for (const auto& d : descs) {
+    const int tiles = ((d.M + 63) / 64) * ((d.N + 63) / 64);
+    maxtiles = std::max(maxtiles, tiles);
+    maxbatch = std::max(maxbatch, d.nbatch);
+    int kt = 0;
+    if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += (d.segK[s] + 15) / 16;
+    else kt = d.KB * ((d.K + 15) / 16);
+    maxkt = std::max(maxkt, kt);
+  }
+  int split = 1;
+  if (mode == GEMM_ATOMIC) {
+    const long long base = (long long)maxtiles * maxbatch * (long long)descs.size();
+    split = (int)std::max<long long>(1, std::min<long long>((target_blocks + base - 1) / base, maxkt / 4));
+    split = std::max(1, std::min(split, 256));
+  }
+  op.g.tA = tA; op.g.tB = tB; op.g.tC = tC; op.g.math = math; op.g.mode = mode;
+  op.g.a_kcontig = akc; op.g.b_kcontig = bkc;
+  op.g.splitk = split;
+  op.g.ndesc = (int)descs.size();
+  op.g.maxbatch = maxbatch;
+  op.g.maxtiles = maxtiles;
+  op.toff = put(P, descs);
+  op.count = (int)descs.size();
+  P.ops.push_back(op);
+}
+
+void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
+  if (a.empty()) return;
+  Op op;
+  op.kind = kind;
+  op.toff = put(P, a);
+  op.count = (int)a.size();
+  P.ops.push_back(op);
+}
+
+void add_fill(Plan& P, void* ptr, size_t bytes) {
+  if (!bytes) return;
+  Op op; op.kind = OP_FILL; op.p0 = ptr; op.bytes = bytes;
+  P.ops.push_back(op);
+}
+
+void add_copy3(Plan& P, const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
+               int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2, double alpha) {
+  Op op; op.kind = OP_COPY; op.p0 = const_cast<void*>(src); op.p1 = dst; op.i0 = tsrc; op.i1 = tdst;
+  const int64_t v[9] = {n0, n1, n2, s0, s1, s2, d0, d1, d2};
+  for (int i = 0; i < 9; ++i) op.c[i] = v[i];
+  op.f0 = alpha;
+  P.ops.push_back(op);
+}
+
+void add_copy(Plan& P, const void* src, int tsrc, void* dst, int tdst, int64_t rows, int64_t cols,
+              int64_t srs, int64_t scs, int64_t drs, int64_t dcs, double alpha) {
+  add_copy3(P, src, tsrc, dst, tdst, 1, rows, cols, 0, srs, scs, 0, drs, dcs, alpha);
+}
+
+void build_key(Plan& P) {
+  P.key.clear();
+  for (auto& op : P.ops) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&op);
+    P.key.insert(P.key.end(), b, b + sizeof(Op));
+  }
+  P.key.insert(P.key.end(), P.table.begin(), P.table.end());
+}
+
+}  // namespace
+
+struct ht_context {
+  int device = 0;
+  std::mutex mu;
+  std::list<Plan> cache;   // most recent first
+};
+
+namespace {
+
+const size_t kCacheMax = 24;
+
+ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
+  build_key(P);
+  void* dtable = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it) {
+      if (it->key == P.key) {
+        dtable = it->dtable;
+        ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
+        break;
+      }
+    }
+    if (!dtable && !P.table.empty()) {
+      if (ctx->cache.size() >= kCacheMax) {
+        HT_HIP(hipDeviceSynchronize());
+        (void)hipFree(ctx->cache.back().dtable);
+        ctx->cache.pop_back();
+      }
+      HT_HIP(hipMalloc(&dtable, P.table.size()));
+      HT_HIP(hipMemcpy(dtable, P.table.data(), P.table.size(), hipMemcpyHostToDevice));
+      Plan c;
+      c.key = P.key;
+      c.dtable = dtable;
+      c.dbytes = P.table.size();
+      ctx->cache.push_front(std::move(c));
+    }
+  }
+  char* tb = reinterpret_cast<char*>(dtable);
+  for (auto& op : P.ops) {
+    hipError_t e = hipSuccess;
+    switch (op.kind) {
+      case OP_GEMM: {
+        GemmLaunch g = op.g;
+        g.descs = reinterpret_cast<const GemmDesc*>(tb + op.toff);
+        e = launch_gemm(g, stream);
+        break;
+      }
+      case OP_CHOL1:
+      case OP_CHOL2:
+        e = launch_chol(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
+                        op.kind == OP_CHOL1 ? 1 : 2, stream, reinterpret_cast<GlobalState*>(op.p0));
+        break;
+      case OP_EIG:
+        e = launch_eig(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, nullptr, stream,
+                       reinterpret_cast<GlobalState*>(op.p0));
+        break;
+      case OP_RANK:
+        e = launch_rank_select(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, op.i0, op.i1,
+                               op.f0, op.i2, op.i3, op.i4, op.i5, reinterpret_cast<GlobalState*>(op.p0),
+                               stream);
+        break;
+      case OP_PROJPREP:
+        e = launch_proj_prep(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
+                             reinterpret_cast<const GlobalState*>(op.p0), stream);
+        break;
+      case OP_SIGMA:
+        e = launch_sigma_from_lam(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
+                                  reinterpret_cast<double* const*>(tb + op.bytes), stream);
+        break;
+      case OP_ROOTNORM:
+        e = launch_root_norm(reinterpret_cast<const double*>(op.p1), op.i0, op.i1,
+                             reinterpret_cast<GlobalState*>(op.p0), stream);
+        break;
+      case OP_FILL:
+        e = launch_fill(op.p0, op.bytes, stream);
+        break;
+      case OP_SETSTATE:
+        e = launch_set_state(reinterpret_cast<GlobalState*>(op.p0), op.scale0, stream);
+        break;
+      case OP_WRITESCALE:
+        e = launch_write_scale(reinterpret_cast<const GlobalState*>(op.p0), reinterpret_cast<long long*>(op.p1),
+                               reinterpret_cast<unsigned int*>(op.p2), reinterpret_cast<int*>(op.bytes ? (void*)op.bytes : nullptr),
+                               op.i0, stream);
+        break;
+      case OP_EGATHER:
+        e = launch_entry_gather(reinterpret_cast<const EntryNode*>(tb + op.toff), op.count, op.c[0],
+                                reinterpret_cast<const int32_t*>(op.p0), op.i0, 0, stream);
+        break;
+      case OP_ENORM:
+        e = launch_entry_normalize(reinterpret_cast<const EntryNode*>(tb + op.toff), op.count, op.c[0], 0, stream);
+        break;
+      case OP_EFINISH:
+        e = launch_entry_finish(reinterpret_cast<const double*>(op.p0), reinterpret_cast<const int32_t*>(op.p1),
+                                op.c[0], op.scale0, reinterpret_cast<double*>(op.p2), stream);
+        break;
+      case OP_COPY:
+        e = launch_copy3(op.p0, op.i0, op.p1, op.i1, op.c[0], op.c[1], op.c[2], op.c[3], op.c[4], op.c[5],
+                         op.c[6], op.c[7], op.c[8], op.f0, stream);
+        break;
+    }
+    if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  return HT_OK;
+}
+
+// ------------------------------------------------------------------ validation
+ht_status check_desc(const ht_desc* X, const char* name, bool need_data = true) {
+  if (!X) return fail(HT_EINVAL, std::string(name) + " is NULL");
+  if (X->d < 2) return fail(HT_EINVAL, std::string(name) + ": d must be >= 2");
+  if (X->d > 4096) return fail(HT_EUNSUPPORTED, std::string(name) + ": d > 4096");
+  if (!X->n || !X->rank) return fail(HT_EINVAL, std::string(name) + ": n or rank is NULL");
+  if (X->frame_dtype != HT_F32 && X->frame_dtype != HT_F64) return fail(HT_EINVAL, std::string(name) + ": bad frame_dtype");
+  if (X->transfer_dtype != HT_F32 && X->transfer_dtype != HT_F64)
+    return fail(HT_EINVAL, std::string(name) + ": bad transfer_dtype");
+  if (need_data && (!X->leaf || !X->leaf_ld || !X->transfer))
+    return fail(HT_EINVAL, std::string(name) + ": leaf, leaf_ld or transfer is NULL");
+  Tree tr(X->d);
+  for (int mu = 0; mu < X->d; ++mu) {
+    if (X->n[mu] < 1) return fail(HT_EINVAL, std::string(name) + ": n_mu must be >= 1");
+    if (X->n[mu] > (int64_t)1 << 31) return fail(HT_EUNSUPPORTED, std::string(name) + ": n_mu too large");
+    if (need_data) {
+      if (!X->leaf[mu]) return fail(HT_EINVAL, std::string(name) + ": leaf pointer is NULL");
+      if (X->leaf_ld[mu] < X->n[mu]) return fail(HT_EINVAL, std::string(name) + ": leaf_ld < n_mu");
+    }
+  }
+  for (int t = 1; t < tr.nn; ++t) {
+    if (X->rank[t] < 1) return fail(HT_EINVAL, std::string(name) + ": ranks must be >= 1");
+    if (need_data && !tr.is_leaf(t) && !X->transfer[t]) return fail(HT_EINVAL, std::string(name) + ": transfer pointer is NULL");
+  }
+  if (need_data && !X->transfer[0]) return fail(HT_EINVAL, std::string(name) + ": root pointer is NULL");
+  return HT_OK;
+}
+
+// ------------------------------------------------------------------ bump allocator over a workspace
+// Address ranges known to the bounds validator (debug builds of a plan only).
+struct Region { uintptr_t lo; size_t bytes; std::string what; };
+static thread_local std::vector<Region>* g_regions = nullptr;
+static void reg(const void* p, size_t bytes, const std::string& what) {
+  if (g_regions && p && bytes) g_regions->push_back({reinterpret_cast<uintptr_t>(p), bytes, what});
+}
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(void* b) : base(reinterpret_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    off = align256(off);
+    void* p = base ? base + off : reinterpret_cast<void*>(off + 256);  // dry run: fake non-null
+    off += bytes;
+    if (base) reg(p, bytes, "workspace");
+    return p;
+  }
+};
+
+// Per-node buffers of the truncation / orthogonalisation.
+struct NodeBufs {
+  int K = 0, rcap = 0;
+  double *G = nullptr, *G2 = nullptr, *Bh = nullptr, *R1 = nullptr, *Ri1 = nullptr, *R = nullptr,
+         *Ri = nullptr, *Q = nullptr, *lam = nullptr, *Qm = nullptr, *scratch = nullptr;
+  void *Rf = nullptr, *QmT = nullptr, *Pm = nullptr;
+  int32_t* rank = nullptr;
+  double* Y = nullptr;      // leaves: n x K sweep-2 temporary; inner: K x K1K2
+  void* Bp = nullptr;       // inner: (I, R_s1, R_s2) o H_t
+  void* Tmp = nullptr;      // inner: mode-3 intermediate
+  void* Qo = nullptr;       // inner: orthogonal transfer tensor
+  double* C = nullptr;      // inner: (Bhat_t, I, I) o Qo
+  void* E1 = nullptr;
+  void* E2 = nullptr;
+};
+
+struct SumInfo {
+  int n_in = 1;
+  std::vector<const ht_desc*> X;
+  std::vector<double> alpha;      // root coefficients incl. scale differences
+  long long scale0 = 0;
+  std::vector<int> K;             // sum rank per node
+  std::vector<std::vector<int>> off;  // off[t][c]: offset of summand c in the sum rank
+};
+
+ht_status sum_info(const ht_desc* X, const double* coef, int n_in, SumInfo& S) {
+  if (n_in < 1 || n_in > MAX_SEG) return fail(HT_EINVAL, "n_in must be in [1, 8]");
+  for (int c = 0; c < n_in; ++c) {
+    ht_status st = check_desc(&X[c], "X[c]");
+    if (st) return st;
+    if (X[c].d != X[0].d) return fail(HT_ESHAPE, "summands must share d");
+    for (int mu = 0; mu < X[0].d; ++mu)
+      if (X[c].n[mu] != X[0].n[mu]) return fail(HT_ESHAPE, "summands must share n");
+    if (X[c].frame_dtype != X[0].frame_dtype || X[c].transfer_dtype != X[0].transfer_dtype)
+      return fail(HT_ESHAPE, "summands must share dtypes");
+  }
+  S.n_in = n_in;
+  const int d = X[0].d, nn = 2 * d - 1;
+  S.X.resize(n_in);
+  long long smax = X[0].log2_scale;
+  for (int c = 0; c < n_in; ++c) { S.X[c] = &X[c]; smax = std::max<long long>(smax, X[c].log2_scale); }
+  S.scale0 = smax;
+  S.alpha.resize(n_in);
+  for (int c = 0; c < n_in; ++c) {
+    const double cf = coef ? coef[c] : 1.0;
+    if (!std::isfinite(cf)) return fail(HT_EINVAL, "coefficients must be finite");
+    S.alpha[c] = std::ldexp(cf, (int)std::max<long long>(-2000, X[c].log2_scale - smax));
+  }
+  S.K.assign(nn, 0);
+  S.off.assign(nn, std::vector<int>(n_in, 0));
+  for (int t = 1; t < nn; ++t)
+    for (int c = 0; c < n_in; ++c) {
+      S.off[t][c] = S.K[t];
+      S.K[t] += X[c].rank[t];
+    }
+  S.K[0] = 1;
+  for (int t = 1; t < nn; ++t)
+    if (S.K[t] > KMAX) return fail(HT_EUNSUPPORTED, "sum rank above 128 at node " + std::to_string(t));
+  return HT_OK;
+}
+
+// Bottom-up orthogonalisation of the lazy sum (Section 3.4) into `B`.
+// Leaves: CholeskyQR2 of W = [U^(1) | ... | U^(n_in)].  Inner nodes:
+// Bp = (I, R_s1, R_s2) o H_t, CholeskyQR2 of M_{2,3}(Bp), Qo = R_t^{-T} M_1(Bp).
+// Root: BDo = R_t1 H_D R_t2^T.
+struct OrthOut {
+  std::vector<NodeBufs> nb;
+  double* HD = nullptr;
+  double* BDo = nullptr;
+  double* T1 = nullptr;
+  GlobalState* st = nullptr;
+};
+
+void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, OrthOut& O,
+               const std::vector<int>& rcap, bool need_proj_bufs, const ht_desc* out,
+               const ht_desc* inplace) {
+  const int nn = tr.nn, d = tr.d;
+  const int T = prec == HT_PREC_MIXED ? F32 : F64;          // forward-product type
+  const int fmath = prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64;
+  const int tsz = esize(T);
+  const ht_desc& X0 = *S.X[0];
+  O.nb.assign(nn, NodeBufs());
+  // ---- zero region (atomic accumulation targets)
+  size_t z0 = align256(A.off);
+  A.off = z0;
+  for (int t = 1; t < nn; ++t) {
+    NodeBufs& b = O.nb[t];
+    b.K = S.K[t];
+    const size_t kk = (size_t)b.K * b.K * 8;
+    b.G = (double*)A.take(kk);
+    b.G2 = (double*)A.take(kk);
+    b.Bh = (double*)A.take(kk);
+  }
+  O.HD = (double*)A.take((size_t)S.K[tr.son1[0]] * S.K[tr.son2[0]] * 8);
+  const size_t zbytes = A.off - z0;
+  void* zptr = A.base ? A.base + z0 : nullptr;
+  reg(zptr, zbytes, "zero region");
+  O.st = (GlobalState*)A.take(sizeof(GlobalState));
+  // ---- the rest
+  for (int t = 1; t < nn; ++t) {
+    NodeBufs& b = O.nb[t];
+    const size_t kk = (size_t)b.K * b.K;
+    b.rcap = rcap.empty() ? b.K : rcap[t];
+    b.R1 = (double*)A.take(kk * 8);
+    b.Ri1 = (double*)A.take(kk * 8);
+    b.R = (double*)A.take(kk * 8);
+    b.Ri = (double*)A.take(kk * 8);
+    b.Rf = A.take(kk * tsz);
+    if (need_proj_bufs) {
+      b.Q = (double*)A.take(kk * 8);
+      b.lam = (double*)A.take(b.K * 8);
+      b.Qm = (double*)A.take((size_t)b.K * b.rcap * 8);
+      b.QmT = A.take((size_t)b.K * b.rcap * tsz);
+      b.rank = (int32_t*)A.take(4);
+      b.scratch = (double*)A.take(eig_scratch_doubles(b.K) * 8);
+    }
+    if (tr.is_leaf(t)) {
+      const int64_t n = X0.n[tr.mode(t)];
+      b.Y = (double*)A.take((size_t)n * b.K * 8);
+      if (need_proj_bufs) b.Pm = A.take((size_t)b.K * b.rcap * tsz);
+    } else {
+      const int K1 = S.K[tr.son1[t]], K2 = S.K[tr.son2[t]];
+      const size_t vol = (size_t)b.K * K1 * K2;
+      b.Bp = A.take(vol * tsz);
+      size_t tmpn = 0;
+      for (int c = 0; c < S.n_in; ++c)
+        tmpn += (size_t)S.X[c]->rank[t] * S.X[c]->rank[tr.son1[t]] * K2;
+      b.Tmp = A.take(tmpn * tsz);
+      b.Y = (double*)A.take(vol * 8);
+      b.Qo = A.take(vol * tsz);
+      if (need_proj_bufs) {
+        b.C = (double*)A.take(vol * 8);
+      }
+    }
+  }
+  const int K1r = S.K[tr.son1[0]], K2r = S.K[tr.son2[0]];
+  O.BDo = (double*)A.take((size_t)K1r * K2r * 8);
+  O.T1 = (double*)A.take((size_t)K1r * K2r * 8);
+  for (int t = 1; t < nn; ++t) {
+    NodeBufs& b = O.nb[t];
+    if (need_proj_bufs && !tr.is_leaf(t)) {
+      const int K1 = S.K[tr.son1[t]], K2 = S.K[tr.son2[t]];
+      b.E1 = A.take((size_t)b.rcap * K1 * K2 * tsz);
+      b.E2 = A.take((size_t)b.rcap * rcap[tr.son1[t]] * K2 * tsz);
+    }
+  }
+
+  // ---- launches
+  {
+    Op op; op.kind = OP_SETSTATE; op.p0 = O.st; op.scale0 = S.scale0;
+    P.ops.push_back(op);
+  }
+  add_fill(P, zptr, zbytes);
+
+  const int fdt = X0.frame_dtype, tdt = X0.transfer_dtype;
+  // leaves: sweep 1 Gram G = W^T W (blocks of summand pairs)
+  {
+    std::vector<GemmDesc> ds;
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      for (int c1 = 0; c1 < S.n_in; ++c1)
+        for (int c2 = 0; c2 < S.n_in; ++c2) {
+          GemmDesc g = blank_desc();
+          g.A = S.X[c1]->leaf[mu]; g.sAm = S.X[c1]->leaf_ld[mu]; g.sAk = 1;
+          g.B = S.X[c2]->leaf[mu]; g.sBk = 1; g.sBn = S.X[c2]->leaf_ld[mu];
+          g.C = O.nb[t].G + (size_t)S.off[t][c1] * S.K[t] + S.off[t][c2];
+          g.sCm = S.K[t]; g.sCn = 1;
+          g.M = S.X[c1]->rank[t]; g.N = S.X[c2]->rank[t]; g.K = (int)X0.n[mu];
+          ds.push_back(g);
+        }
+    }
+    add_gemm(P, ds, fdt, fdt, F64, prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64, GEMM_ATOMIC, true, true);
+  }
+  auto small_args = [&](const std::vector<int>& nodes, double tol) {
+    std::vector<SmallArgs> v;
+    for (int t : nodes) {
+      NodeBufs& b = O.nb[t];
+      SmallArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.K = b.K; a.node = t; a.rcap = b.rcap;
+      a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1; a.R = b.R; a.Ri = b.Ri; a.Rf = b.Rf;
+      a.rf_type = T; a.tol_rel = tol;
+      a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rank_dev = b.rank; a.scratch = b.scratch;
+      a.Bh = b.Bh;
+      v.push_back(a);
+    }
+    return v;
+  };
+  std::vector<int> leaves;
+  for (int mu = 0; mu < d; ++mu) leaves.push_back(tr.leaf_node[mu]);
+  {
+    Op op;
+    auto a = small_args(leaves, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
+    add_small(P, OP_CHOL1, a);
+    P.ops.back().p0 = O.st;
+  }
+  // sweep 2: Y = W R1^{-1} (float64), G2 = Y^T Y
+  {
+    std::vector<GemmDesc> ds;
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      GemmDesc g = blank_desc();
+      g.nseg = S.n_in;
+      for (int c = 0; c < S.n_in; ++c) {
+        g.segA[c] = S.X[c]->leaf[mu];
+        g.segAk[c] = S.X[c]->leaf_ld[mu];
+        g.segBoff[c] = (int64_t)S.off[t][c] * S.K[t];
+        g.segK[c] = S.X[c]->rank[t];
+      }
+      g.A = S.X[0]->leaf[mu]; g.sAm = 1;
+      g.B = O.nb[t].Ri1; g.sBk = S.K[t]; g.sBn = 1;
+      g.C = O.nb[t].Y; g.sCm = 1; g.sCn = X0.n[mu];
+      g.M = (int)X0.n[mu]; g.N = S.K[t]; g.K = 0;
+      ds.push_back(g);
+    }
+    add_gemm(P, ds, fdt, F64, F64, MATH_F64, GEMM_STORE, false, false);
+    ds.clear();
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      GemmDesc g = blank_desc();
+      g.A = O.nb[t].Y; g.sAm = X0.n[mu]; g.sAk = 1;
+      g.B = O.nb[t].Y; g.sBk = 1; g.sBn = X0.n[mu];
+      g.C = O.nb[t].G2; g.sCm = S.K[t]; g.sCn = 1;
+      g.M = S.K[t]; g.N = S.K[t]; g.K = (int)X0.n[mu];
+      ds.push_back(g);
+    }
+    add_gemm(P, ds, F64, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+  }
+  {
+    auto a = small_args(leaves, 1e-13);
+    add_small(P, OP_CHOL2, a);
+    P.ops.back().p0 = O.st;
+  }
+  // inner nodes by height
+  const int H = tr.height[0];
+  for (int h = 1; h < H; ++h) {
+    std::vector<int> nodes;
+    for (int t = 1; t < nn; ++t)
+      if (!tr.is_leaf(t) && tr.height[t] == h) nodes.push_back(t);
+    if (nodes.empty()) continue;
+    // mode-3: Tmp_c = B^(c) x_3 R_s2[:, o2 : o2+k2c]
+    std::vector<GemmDesc> d3, d2;
+    for (int t : nodes) {
+      const int s1 = tr.son1[t], s2 = tr.son2[t];
+      const int K1 = S.K[s1], K2 = S.K[s2];
+      size_t toff = 0;
+      for (int c = 0; c < S.n_in; ++c) {
+        const int kt = S.X[c]->rank[t], k1 = S.X[c]->rank[s1], k2 = S.X[c]->rank[s2];
+        GemmDesc g = blank_desc();
+        g.A = S.X[c]->transfer[t]; g.sAm = k2; g.sAk = 1;
+        g.B = (const char*)O.nb[s2].Rf + (size_t)S.off[s2][c] * tsz; g.sBk = 1; g.sBn = K2;
+        void* tmpc = (char*)O.nb[t].Tmp + toff * tsz;
+        g.C = tmpc; g.sCm = K2; g.sCn = 1;
+        g.M = kt * k1; g.N = K2; g.K = k2;
+        d3.push_back(g);
+        // mode-2: Bp[o_t + i] = R_s1[:, o1 : o1+k1c] Tmp_c[i]
+        GemmDesc h2 = blank_desc();
+        h2.A = (const char*)O.nb[s1].Rf + (size_t)S.off[s1][c] * tsz; h2.sAm = K1; h2.sAk = 1;
+        h2.B = tmpc; h2.sBk = K2; h2.sBn = 1; h2.sBb = (int64_t)k1 * K2;
+        h2.C = (char*)O.nb[t].Bp + (size_t)S.off[t][c] * K1 * K2 * tsz; h2.sCm = K2; h2.sCn = 1;
+        h2.sCb = (int64_t)K1 * K2;
+        h2.M = K1; h2.N = K2; h2.K = k1; h2.nbatch = kt;
+        d2.push_back(h2);
+        toff += (size_t)kt * k1 * K2;
+      }
+    }
+    add_gemm(P, d3, tdt, T, T, fmath, GEMM_STORE, true, true);
+    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false);
+    // sweep 1: G = M1(Bp) M1(Bp)^T in float64
+    std::vector<GemmDesc> dg;
+    for (int t : nodes) {
+      const int K1 = S.K[tr.son1[t]], K2 = S.K[tr.son2[t]];
+      const int64_t w = (int64_t)K1 * K2;
+      GemmDesc g = blank_desc();
+      g.A = O.nb[t].Bp; g.sAm = w; g.sAk = 1;
+      g.B = O.nb[t].Bp; g.sBk = 1; g.sBn = w;
+      g.C = O.nb[t].G; g.sCm = S.K[t]; g.sCn = 1;
+      g.M = S.K[t]; g.N = S.K[t]; g.K = (int)w;
+      dg.push_back(g);
+    }
+    add_gemm(P, dg, T, T, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    {
+      auto a = small_args(nodes, 1e-12);
+      add_small(P, OP_CHOL1, a);
+      P.ops.back().p0 = O.st;
+    }
+    // sweep 2: Y = R1^{-T} M1(Bp) (float64), G2 = Y Y^T
+    std::vector<GemmDesc> dy, dg2, dq;
+    for (int t : nodes) {
+      const int K1 = S.K[tr.son1[t]], K2 = S.K[tr.son2[t]];
+      const int64_t w = (int64_t)K1 * K2;
+      GemmDesc g = blank_desc();
+      g.A = O.nb[t].Ri1; g.sAm = 1; g.sAk = S.K[t];
+      g.B = O.nb[t].Bp; g.sBk = w; g.sBn = 1;
+      g.C = O.nb[t].Y; g.sCm = w; g.sCn = 1;
+      g.M = S.K[t]; g.N = (int)w; g.K = S.K[t];
+      dy.push_back(g);
+      GemmDesc h = blank_desc();
+      h.A = O.nb[t].Y; h.sAm = w; h.sAk = 1;
+      h.B = O.nb[t].Y; h.sBk = 1; h.sBn = w;
+      h.C = O.nb[t].G2; h.sCm = S.K[t]; h.sCn = 1;
+      h.M = S.K[t]; h.N = S.K[t]; h.K = (int)w;
+      dg2.push_back(h);
+      GemmDesc q = blank_desc();
+      q.A = O.nb[t].Ri; q.sAm = 1; q.sAk = S.K[t];
+      q.B = O.nb[t].Bp; q.sBk = w; q.sBn = 1;
+      const bool write_user = inplace != nullptr;
+      q.C = write_user ? inplace->transfer[t] : O.nb[t].Qo; q.sCm = w; q.sCn = 1;
+      q.M = S.K[t]; q.N = (int)w; q.K = S.K[t];
+      dq.push_back(q);
+    }
+    add_gemm(P, dy, F64, T, F64, MATH_F64, GEMM_STORE, false, false);
+    add_gemm(P, dg2, F64, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    {
+      auto a = small_args(nodes, 1e-13);
+      add_small(P, OP_CHOL2, a);
+      P.ops.back().p0 = O.st;
+    }
+    add_gemm(P, dq, F64, T, inplace ? inplace->transfer_dtype : T, MATH_F64, GEMM_STORE, false, false);
+  }
+  // root: HD = blockdiag(alpha_c B_D^(c)); BDo = R_t1 HD R_t2^T
+  const int t1 = tr.son1[0], t2 = tr.son2[0];
+  for (int c = 0; c < S.n_in; ++c) {
+    const int r1 = S.X[c]->rank[t1], r2 = S.X[c]->rank[t2];
+    add_copy(P, S.X[c]->transfer[0], F64, O.HD + (size_t)S.off[t1][c] * K2r + S.off[t2][c], F64, r1, r2, r2, 1,
+             K2r, 1, S.alpha[c]);
+  }
+  {
+    std::vector<GemmDesc> a1, a2;
+    GemmDesc g = blank_desc();
+    g.A = O.nb[t1].R; g.sAm = K1r; g.sAk = 1;
+    g.B = O.HD; g.sBk = K2r; g.sBn = 1;
+    g.C = O.T1; g.sCm = K2r; g.sCn = 1;
+    g.M = K1r; g.N = K2r; g.K = K1r;
+    a1.push_back(g);
+    add_gemm(P, a1, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    GemmDesc h = blank_desc();
+    h.A = O.T1; h.sAm = K2r; h.sAk = 1;
+    h.B = O.nb[t2].R; h.sBk = 1; h.sBn = K2r;
+    h.C = inplace ? inplace->transfer[0] : O.BDo; h.sCm = K2r; h.sCn = 1;
+    h.M = K1r; h.N = K2r; h.K = K2r;
+    a2.push_back(h);
+    add_gemm(P, a2, F64, F64, F64, MATH_F64, GEMM_STORE, true, true);
+  }
+  (void)out;
+}
+
+// Top-down Gramians (eqs. (acctransferroot), (acctransferSon1/2)) from the
+// orthogonal root BDo and orthogonal transfer tensors Qo[t] (type tq).
+void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vector<NodeBufs>& nb,
+                   const double* BDo, GlobalState* st, const std::vector<const void*>& Qo, int tq) {
+  const int t1 = tr.son1[0], t2 = tr.son2[0];
+  const int K1r = K[t1], K2r = K[t2];
+  {
+    Op op; op.kind = OP_ROOTNORM; op.p0 = st; op.p1 = const_cast<double*>(BDo); op.i0 = K1r; op.i1 = K2r;
+    P.ops.push_back(op);
+  }
+  {
+    std::vector<GemmDesc> a, b;
+    GemmDesc g = blank_desc();
+    g.A = BDo; g.sAm = K2r; g.sAk = 1;
+    g.B = BDo; g.sBk = 1; g.sBn = K2r;
+    g.C = nb[t1].Bh; g.sCm = K1r; g.sCn = 1;
+    g.M = K1r; g.N = K1r; g.K = K2r; g.alpha_dev = &st->alpha_gram;
+    a.push_back(g);
+    add_gemm(P, a, F64, F64, F64, MATH_F64, GEMM_STORE, true, true);
+    GemmDesc h = blank_desc();
+    h.A = BDo; h.sAm = 1; h.sAk = K2r;
+    h.B = BDo; h.sBk = K2r; h.sBn = 1;
+    h.C = nb[t2].Bh; h.sCm = K2r; h.sCn = 1;
+    h.M = K2r; h.N = K2r; h.K = K1r; h.alpha_dev = &st->alpha_gram;
+    b.push_back(h);
+    add_gemm(P, b, F64, F64, F64, MATH_F64, GEMM_STORE, false, false);
+  }
+  const int D = tr.max_depth();
+  for (int dep = 1; dep < D; ++dep) {
+    std::vector<GemmDesc> dc, ds1, ds2;
+    for (int t = 1; t < tr.nn; ++t) {
+      if (tr.is_leaf(t) || tr.depth[t] != dep) continue;
+      const int s1 = tr.son1[t], s2 = tr.son2[t];
+      const int Kt = K[t], K1 = K[s1], K2 = K[s2];
+      const int64_t w = (int64_t)K1 * K2;
+      GemmDesc g = blank_desc();
+      g.A = nb[t].Bh; g.sAm = Kt; g.sAk = 1;
+      g.B = Qo[t]; g.sBk = w; g.sBn = 1;
+      g.C = nb[t].C; g.sCm = w; g.sCn = 1;
+      g.M = Kt; g.N = (int)w; g.K = Kt;
+      dc.push_back(g);
+      // Bhat_s1[p,q] = sum_{i,l} Qo[i,p,l] C[i,q,l]
+      GemmDesc h = blank_desc();
+      h.A = Qo[t]; h.sAm = K2; h.sAk = 1; h.sAkb = w;
+      h.B = nb[t].C; h.sBk = 1; h.sBn = K2; h.sBkb = w;
+      h.C = nb[s1].Bh; h.sCm = K1; h.sCn = 1;
+      h.M = K1; h.N = K1; h.K = K2; h.KB = Kt;
+      ds1.push_back(h);
+      // Bhat_s2[p,q] = sum_{i,j} Qo[i,j,p] C[i,j,q]
+      GemmDesc q = blank_desc();
+      q.A = Qo[t]; q.sAm = 1; q.sAk = K2;
+      q.B = nb[t].C; q.sBk = K2; q.sBn = 1;
+      q.C = nb[s2].Bh; q.sCm = K2; q.sCn = 1;
+      q.M = K2; q.N = K2; q.K = Kt * K1;
+      ds2.push_back(q);
+    }
+    add_gemm(P, dc, F64, tq, F64, MATH_F64, GEMM_STORE, true, false);
+    add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false);
+  }
+}
+
+}  // namespace
+
+// ================================================================== ABI
+extern "C" {
+
+int32_t ht_version(void) { return 1; }
+
+const char* ht_status_string(ht_status s) {
+  switch (s) {
+    case HT_OK: return "ok";
+    case HT_EINVAL: return "invalid argument";
+    case HT_ESHAPE: return "inconsistent shapes";
+    case HT_EWORKSPACE: return "workspace too small or misaligned";
+    case HT_EDEVICE: return "HIP runtime error";
+    case HT_EUNSUPPORTED: return "unsupported size";
+  }
+  return "unknown status";
+}
+
+const char* ht_last_error(void) { return g_last_error.c_str(); }
+
+ht_status ht_create_context(int device, ht_context** out) {
+  if (!out) return fail(HT_EINVAL, "out is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(HT_EDEVICE, "no such HIP device");
+  ht_context* c = new ht_context();
+  c->device = device;
+  *out = c;
+  return HT_OK;
+}
+
+void ht_destroy_context(ht_context* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  for (auto& p : ctx->cache) (void)hipFree(p.dtable);
+  delete ctx;
+}
+
+ht_status ht_tree(int32_t d, int32_t* parent, int32_t* son1, int32_t* son2, int32_t* lo, int32_t* hi,
+                  int32_t* depth, int32_t* height) {
+  if (d < 2) return fail(HT_EINVAL, "d must be >= 2");
+  Tree tr(d);
+  for (int t = 0; t < tr.nn; ++t) {
+    if (parent) parent[t] = tr.parent[t];
+    if (son1) son1[t] = tr.son1[t];
+    if (son2) son2[t] = tr.son2[t];
+    if (lo) lo[t] = tr.lo[t];
+    if (hi) hi[t] = tr.hi[t];
+    if (depth) depth[t] = tr.depth[t];
+    if (height) height[t] = tr.height[t];
+  }
+  return HT_OK;
+}
+
+// ------------------------------------------------------------------ truncation
+static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
+                                const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
+                                int64_t* out_scale, uint32_t* flags, double* out_sigma, void* ws,
+                                Plan& P, size_t* need) {
+  (void)ctx;
+  if (!opts) return fail(HT_EINVAL, "opts is NULL");
+  if (opts->mode != HT_RANK_FIXED && opts->mode != HT_RANK_TOL) return fail(HT_EINVAL, "bad rank mode");
+  if (opts->precision != HT_PREC_FP64 && opts->precision != HT_PREC_MIXED) return fail(HT_EINVAL, "bad precision");
+  if (opts->mode == HT_RANK_FIXED && !opts->ranks) return fail(HT_EINVAL, "opts->ranks is NULL");
+  if (opts->mode == HT_RANK_TOL && !(opts->eps >= 0.0)) return fail(HT_EINVAL, "eps must be >= 0");
+  if (!X) return fail(HT_EINVAL, "X is NULL");
+  SumInfo S;
+  ht_status st = sum_info(X, coef, n_in, S);
+  if (st) return st;
+  const int d = X[0].d;
+  Tree tr(d);
+  const int nn = tr.nn;
+  std::vector<int> rcap(nn, 1);
+  for (int t = 1; t < nn; ++t) {
+    if (opts->mode == HT_RANK_FIXED) {
+      if (opts->ranks[t] < 1) return fail(HT_EINVAL, "fixed ranks must be >= 1");
+      rcap[t] = std::min(opts->ranks[t], S.K[t]);
+    } else {
+      rcap[t] = opts->max_rank > 0 ? std::min(opts->max_rank, S.K[t]) : S.K[t];
+    }
+  }
+  if (opts->mode == HT_RANK_TOL) {  // the sons of the root share one rank
+    const int r = std::min(rcap[tr.son1[0]], rcap[tr.son2[0]]);
+    rcap[tr.son1[0]] = rcap[tr.son2[0]] = r;
+  }
+  if (!need) {
+    st = check_desc(out, "out");
+    if (st) return st;
+    if (out->d != d) return fail(HT_ESHAPE, "out->d differs");
+    for (int mu = 0; mu < d; ++mu)
+      if (out->n[mu] != X[0].n[mu]) return fail(HT_ESHAPE, "out->n differs");
+    for (int t = 1; t < nn; ++t)
+      if (out->rank[t] != rcap[t])
+        return fail(HT_ESHAPE, "out->rank[" + std::to_string(t) + "] must be " + std::to_string(rcap[t]));
+    if (!out_scale) return fail(HT_EINVAL, "out_log2_scale is NULL");
+  }
+  const int prec = opts->precision;
+  const int T = prec == HT_PREC_MIXED ? F32 : F64;
+  const int fmath = prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64;
+  const int tsz = esize(T);
+  Arena A(ws);
+  OrthOut O;
+  plan_orth(P, tr, S, prec, A, O, rcap, true, out, nullptr);
+  std::vector<const void*> Qo(nn, nullptr);
+  for (int t = 1; t < nn; ++t) Qo[t] = O.nb[t].Qo;
+  plan_gramians(P, tr, S.K, O.nb, O.BDo, O.st, Qo, T);
+  // eigen-decompositions of all Gramians, ranks, masked eigenvectors
+  std::vector<int> nonroot;
+  for (int t = 1; t < nn; ++t) nonroot.push_back(t);
+  std::vector<SmallArgs> sa;
+  for (int t : nonroot) {
+    NodeBufs& b = O.nb[t];
+    SmallArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.K = b.K; a.node = t; a.rcap = b.rcap; a.rfix = opts->mode == HT_RANK_FIXED ? rcap[t] : 0;
+    a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rf_type = T;
+    a.rank_dev = out_ranks ? out_ranks + t : b.rank;
+    a.scratch = b.scratch; a.Bh = b.Bh;
+    a.sigma_out = out_sigma ? out_sigma + (size_t)t * KMAX : nullptr;
+    sa.push_back(a);
+  }
+  add_small(P, OP_EIG, sa);
+  P.ops.back().p0 = O.st;
+  add_small(P, OP_RANK, sa);
+  {
+    Op& op = P.ops.back();
+    op.p0 = O.st; op.i0 = d; op.i1 = opts->mode; op.f0 = opts->eps; op.i2 = opts->eps_relative ? 1 : 0;
+    op.i3 = opts->max_rank; op.i4 = tr.son1[0]; op.i5 = tr.son2[0];
+  }
+  add_small(P, OP_PROJPREP, sa);
+  P.ops.back().p0 = O.st;
+  // projections (eq. (nodewisetruncation), eq. (transfertransformationtrunc), root rule)
+  {
+    std::vector<GemmDesc> dp, du, d1, d2, d3;
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      NodeBufs& b = O.nb[t];
+      GemmDesc g = blank_desc();  // Pm = R^{-1} Qm
+      g.A = b.Ri; g.sAm = b.K; g.sAk = 1;
+      g.B = b.Qm; g.sBk = b.rcap; g.sBn = 1;
+      g.C = b.Pm; g.sCm = b.rcap; g.sCn = 1;
+      g.M = b.K; g.N = b.rcap; g.K = b.K;
+      dp.push_back(g);
+      GemmDesc u = blank_desc();  // U_new = W Pm
+      u.nseg = S.n_in;
+      for (int c = 0; c < S.n_in; ++c) {
+        u.segA[c] = S.X[c]->leaf[mu];
+        u.segAk[c] = S.X[c]->leaf_ld[mu];
+        u.segBoff[c] = (int64_t)S.off[t][c] * b.rcap;
+        u.segK[c] = S.X[c]->rank[t];
+      }
+      u.A = S.X[0]->leaf[mu]; u.sAm = 1;
+      u.B = b.Pm; u.sBk = b.rcap; u.sBn = 1;
+      u.C = need ? nullptr : out->leaf[mu]; u.sCm = 1; u.sCn = need ? 1 : out->leaf_ld[mu];
+      u.M = (int)X[0].n[mu]; u.N = b.rcap;
+      du.push_back(u);
+    }
+    for (int t = 1; t < nn; ++t) {
+      if (tr.is_leaf(t)) continue;
+      NodeBufs& b = O.nb[t];
+      const int s1 = tr.son1[t], s2 = tr.son2[t];
+      const int K1 = S.K[s1], K2 = S.K[s2];
+      const int64_t w = (int64_t)K1 * K2;
+      GemmDesc g = blank_desc();  // E1 = Qm_t^T M1(Qo)
+      g.A = b.QmT; g.sAm = b.K; g.sAk = 1;
+      g.B = b.Qo; g.sBk = w; g.sBn = 1;
+      g.C = b.E1; g.sCm = w; g.sCn = 1;
+      g.M = b.rcap; g.N = (int)w; g.K = b.K;
+      d1.push_back(g);
+      GemmDesc h = blank_desc();  // E2[a] = Qm_s1^T E1[a]
+      h.A = O.nb[s1].QmT; h.sAm = K1; h.sAk = 1;
+      h.B = b.E1; h.sBk = K2; h.sBn = 1; h.sBb = w;
+      h.C = b.E2; h.sCm = K2; h.sCn = 1; h.sCb = (int64_t)O.nb[s1].rcap * K2;
+      h.M = O.nb[s1].rcap; h.N = K2; h.K = K1; h.nbatch = b.rcap;
+      d2.push_back(h);
+      GemmDesc q = blank_desc();  // B_new = M12(E2) Qm_s2
+      q.A = b.E2; q.sAm = K2; q.sAk = 1;
+      q.B = O.nb[s2].QmT; q.sBk = 1; q.sBn = K2;
+      q.C = need ? nullptr : out->transfer[t]; q.sCm = O.nb[s2].rcap; q.sCn = 1;
+      q.M = b.rcap * O.nb[s1].rcap; q.N = O.nb[s2].rcap; q.K = K2;
+      d3.push_back(q);
+    }
+    add_gemm(P, dp, F64, F64, T, MATH_F64, GEMM_STORE, true, false);
+    add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false);
+    add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false);
+    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false);
+    add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true);
+    // root: Qm_t1^T BDo Qm_t2
+    const int t1 = tr.son1[0], t2 = tr.son2[0];
+    const int K1r = S.K[t1], K2r = S.K[t2];
+    std::vector<GemmDesc> r1, r2;
+    GemmDesc g = blank_desc();
+    g.A = O.nb[t1].Qm; g.sAm = 1; g.sAk = O.nb[t1].rcap;
+    g.B = O.BDo; g.sBk = K2r; g.sBn = 1;
+    g.C = O.T1; g.sCm = K2r; g.sCn = 1;
+    g.M = O.nb[t1].rcap; g.N = K2r; g.K = K1r;
+    r1.push_back(g);
+    add_gemm(P, r1, F64, F64, F64, MATH_F64, GEMM_STORE, false, false);
+    GemmDesc h = blank_desc();
+    h.A = O.T1; h.sAm = K2r; h.sAk = 1;
+    h.B = O.nb[t2].Qm; h.sBk = O.nb[t2].rcap; h.sBn = 1;
+    h.C = need ? nullptr : out->transfer[0]; h.sCm = O.nb[t2].rcap; h.sCn = 1;
+    h.M = O.nb[t1].rcap; h.N = O.nb[t2].rcap; h.K = K2r;
+    r2.push_back(h);
+    add_gemm(P, r2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+  }
+  {
+    Op op; op.kind = OP_WRITESCALE; op.p0 = O.st; op.p1 = out_scale; op.p2 = flags;
+    op.bytes = (size_t)(out_ranks ? (void*)out_ranks : nullptr);
+    P.ops.push_back(op);
+  }
+  (void)tsz;
+  if (need) *need = align256(A.off) + 256;
+  return HT_OK;
+}
+
+ht_status ht_truncate_workspace(ht_context* ctx, const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts,
+                                size_t* bytes) {
+  if (!bytes) return fail(HT_EINVAL, "bytes is NULL");
+  Plan P;
+  for (int c = 0; c < n_in && X; ++c) {
+    ht_status s = check_desc(&X[c], "X[c]", false);
+    if (s) return s;
+  }
+  // a dry run needs descriptors with data pointers; substitute placeholders
+  std::vector<ht_desc> Xs(X, X + std::max(0, n_in));
+  std::vector<std::vector<void*>> leaves(n_in), trans(n_in);
+  std::vector<std::vector<int64_t>> lds(n_in);
+  for (int c = 0; c < n_in; ++c) {
+    leaves[c].assign(X[c].d, (void*)256);
+    trans[c].assign(2 * X[c].d - 1, (void*)256);
+    lds[c].assign(X[c].n, X[c].n + X[c].d);
+    if (!X[c].leaf) Xs[c].leaf = leaves[c].data();
+    if (!X[c].transfer) Xs[c].transfer = trans[c].data();
+    if (!X[c].leaf_ld) Xs[c].leaf_ld = lds[c].data();
+  }
+  return build_truncate(ctx, Xs.data(), nullptr, n_in, opts, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, P, bytes);
+}
+
+ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
+                      const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
+                      int64_t* out_log2_scale, uint32_t* flags, double* out_sigma, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  ht_status st = ht_truncate_workspace(ctx, X, n_in, opts, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_truncate(ctx, X, coef, n_in, opts, out, out_ranks, out_log2_scale, flags, out_sigma, ws, P,
+                      nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ orthogonalisation
+static ht_status build_orth(const ht_desc* X, int precision, int64_t* out_scale, uint32_t* flags, void* ws,
+                            Plan& P, size_t* need) {
+  if (precision != HT_PREC_FP64 && precision != HT_PREC_MIXED) return fail(HT_EINVAL, "bad precision");
+  SumInfo S;
+  ht_status st = sum_info(X, nullptr, 1, S);
+  if (st) return st;
+  Tree tr(X->d);
+  for (int mu = 0; mu < X->d; ++mu)
+    if (X->n[mu] < X->rank[tr.leaf_node[mu]]) return fail(HT_EUNSUPPORTED, "orthogonalisation needs n_mu >= k_mu");
+  if (!need && !out_scale) return fail(HT_EINVAL, "out_log2_scale is NULL");
+  Arena A(ws);
+  OrthOut O;
+  plan_orth(P, tr, S, precision, A, O, {}, false, nullptr, X);
+  // leaves: Q = W R^{-1} into the frame buffer (via the sweep-2 temporary)
+  std::vector<GemmDesc> dq;
+  for (int mu = 0; mu < X->d; ++mu) {
+    const int t = tr.leaf_node[mu];
+    GemmDesc g = blank_desc();
+    g.A = X->leaf[mu]; g.sAm = 1; g.sAk = X->leaf_ld[mu];
+    g.B = O.nb[t].Ri; g.sBk = S.K[t]; g.sBn = 1;
+    g.C = O.nb[t].Y; g.sCm = 1; g.sCn = X->n[mu];
+    g.M = (int)X->n[mu]; g.N = S.K[t]; g.K = S.K[t];
+    dq.push_back(g);
+  }
+  add_gemm(P, dq, X->frame_dtype, F64, F64, MATH_F64, GEMM_STORE, false, false);
+  for (int mu = 0; mu < X->d; ++mu) {
+    const int t = tr.leaf_node[mu];
+    add_copy(P, O.nb[t].Y, F64, X->leaf[mu], X->frame_dtype, X->n[mu], S.K[t], 1, X->n[mu], 1,
+             X->leaf_ld[mu], 1.0);
+  }
+  Op op; op.kind = OP_WRITESCALE; op.p0 = O.st; op.p1 = out_scale; op.p2 = flags;
+  P.ops.push_back(op);
+  if (need) *need = align256(A.off) + 256;
+  return HT_OK;
+}
+
+ht_status ht_orthogonalize_workspace(ht_context* ctx, const ht_desc* X, int32_t precision, size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(HT_EINVAL, "NULL argument");
+  ht_status s = check_desc(X, "X", false);
+  if (s) return s;
+  std::vector<void*> lv(X->d, (void*)256), tv(2 * X->d - 1, (void*)256);
+  std::vector<int64_t> ld(X->n, X->n + X->d);
+  ht_desc Y = *X;
+  if (!Y.leaf) Y.leaf = lv.data();
+  if (!Y.transfer) Y.transfer = tv.data();
+  if (!Y.leaf_ld) Y.leaf_ld = ld.data();
+  Plan P;
+  return build_orth(&Y, precision, nullptr, nullptr, nullptr, P, bytes);
+}
+
+ht_status ht_orthogonalize(ht_context* ctx, const ht_desc* X, int32_t precision, int64_t* out_log2_scale,
+                           uint32_t* flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  ht_status st = ht_orthogonalize_workspace(ctx, X, precision, &need);
+  if (st) return st;
+  st = check_desc(X, "X");
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_orth(X, precision, out_log2_scale, flags, ws, P, nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ Gramians of an orthogonal tensor
+static ht_status build_gram(const ht_desc* X, double* const* bhat, double* const* sigma, int64_t* out_units,
+                            void* ws, Plan& P, size_t* need) {
+  Tree tr(X->d);
+  const int nn = tr.nn;
+  std::vector<int> K(nn, 1);
+  for (int t = 1; t < nn; ++t) {
+    K[t] = X->rank[t];
+    if (K[t] > KMAX) return fail(HT_EUNSUPPORTED, "rank above 128");
+  }
+  if (!need) {
+    if (!bhat) return fail(HT_EINVAL, "bhat is NULL");
+    for (int t = 1; t < nn; ++t)
+      if (!bhat[t]) return fail(HT_EINVAL, "bhat[t] is NULL");
+  }
+  Arena A(ws);
+  std::vector<NodeBufs> nb(nn);
+  size_t z0 = A.off;
+  for (int t = 1; t < nn; ++t) {
+    nb[t].K = K[t];
+    nb[t].Bh = need ? (double*)A.take((size_t)K[t] * K[t] * 8) : bhat[t];
+  }
+  if (!need) {
+    // the Gramians are accumulated atomically into the caller's arrays: clear them
+  }
+  GlobalState* st = (GlobalState*)A.take(sizeof(GlobalState));
+  for (int t = 1; t < nn; ++t) {
+    if (tr.is_leaf(t)) continue;
+    nb[t].C = (double*)A.take((size_t)K[t] * K[tr.son1[t]] * K[tr.son2[t]] * 8);
+  }
+  const bool want_sigma = sigma != nullptr;
+  for (int t = 1; t < nn && want_sigma; ++t) {
+    nb[t].Q = (double*)A.take((size_t)K[t] * K[t] * 8);
+    nb[t].lam = (double*)A.take((size_t)K[t] * 8);
+    nb[t].scratch = (double*)A.take(eig_scratch_doubles(K[t]) * 8);
+  }
+  {
+    Op op; op.kind = OP_SETSTATE; op.p0 = st; op.scale0 = X->log2_scale;
+    P.ops.push_back(op);
+  }
+  if (!need)
+    for (int t = 1; t < nn; ++t) add_fill(P, nb[t].Bh, (size_t)K[t] * K[t] * 8);
+  std::vector<const void*> Qo(nn, nullptr);
+  for (int t = 1; t < nn; ++t) Qo[t] = X->transfer ? X->transfer[t] : nullptr;
+  plan_gramians(P, tr, K, nb, (const double*)X->transfer[0], st, Qo, X->transfer_dtype);
+  if (want_sigma) {
+    std::vector<SmallArgs> sa;
+    std::vector<double*> sp;
+    for (int t = 1; t < nn; ++t) {
+      SmallArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.K = K[t]; a.node = t; a.Q = nb[t].Q; a.lam = nb[t].lam; a.scratch = nb[t].scratch; a.Bh = nb[t].Bh;
+      sa.push_back(a);
+      sp.push_back(sigma[t]);
+    }
+    add_small(P, OP_EIG, sa);
+    P.ops.back().p0 = st;
+    add_small(P, OP_SIGMA, sa);
+    P.ops.back().bytes = put(P, sp);
+  }
+  if (out_units) {
+    Op op; op.kind = OP_WRITESCALE; op.p0 = st; op.p1 = out_units; op.p2 = nullptr; op.i0 = 1;
+    P.ops.push_back(op);
+  }
+  if (need) *need = align256(A.off) + 256;
+  (void)z0;
+  return HT_OK;
+}
+
+ht_status ht_gramians_workspace(ht_context* ctx, const ht_desc* X, size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(HT_EINVAL, "NULL argument");
+  ht_status s = check_desc(X, "X", false);
+  if (s) return s;
+  std::vector<void*> tv(2 * X->d - 1, (void*)256);
+  ht_desc Y = *X;
+  if (!Y.transfer) Y.transfer = tv.data();
+  Plan P;
+  // sized with the optional eigensolver buffers (sigma requested)
+  static double* const placeholder[1] = {nullptr};
+  return build_gram(&Y, nullptr, placeholder, nullptr, nullptr, P, bytes);
+}
+
+ht_status ht_gramians(ht_context* ctx, const ht_desc* X, double* const* bhat, double* const* sigma,
+                      int64_t* out_log2_units, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  ht_status st = ht_gramians_workspace(ctx, X, &need);
+  if (st) return st;
+  st = check_desc(X, "X");
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_gram(X, bhat, sigma, out_log2_units, ws, P, nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ entries
+static size_t entries_chunk(const ht_desc* X, int64_t m, size_t* per_index) {
+  Tree tr(X->d);
+  size_t per = 0;
+  for (int t = 0; t < tr.nn; ++t) per += (size_t)(t == 0 ? 1 : X->rank[t]) * 8 + 4 + 16;
+  *per_index = per;
+  const size_t cap = (size_t)1 << 31;
+  size_t ch = std::max<size_t>(1024, cap / per);
+  return (size_t)std::min<int64_t>(m, (int64_t)ch);
+}
+
+static ht_status build_entries(const ht_desc* X, int64_t m, const int32_t* idx, double* out, void* ws, Plan& P,
+                               size_t* need) {
+  Tree tr(X->d);
+  const int nn = tr.nn, d = X->d;
+  for (int t = 1; t < nn; ++t)
+    if (X->rank[t] > 4096) return fail(HT_EUNSUPPORTED, "rank too large for entries");
+  size_t per = 0;
+  const int64_t ch = m > 0 ? (int64_t)entries_chunk(X, m, &per) : 0;
+  Arena A(ws);
+  std::vector<double*> rows(nn);
+  std::vector<int32_t*> expo(nn);
+  for (int t = 0; t < nn; ++t) {
+    const int k = t == 0 ? 1 : X->rank[t];
+    rows[t] = (double*)A.take((size_t)std::max<int64_t>(ch, 1) * k * 8);
+    expo[t] = (int32_t*)A.take((size_t)std::max<int64_t>(ch, 1) * 4);
+  }
+  if (need) {
+    *need = align256(A.off) + 256;
+    return HT_OK;
+  }
+  const int H = tr.height[0];
+  for (int64_t c0 = 0; c0 < m; c0 += ch) {
+    const int64_t mc = std::min<int64_t>(ch, m - c0);
+    // leaves
+    std::vector<EntryNode> lv;
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      EntryNode e;
+      std::memset(&e, 0, sizeof(e));
+      e.k = X->rank[t]; e.mode = mu; e.tdtype = X->frame_dtype; e.U = X->leaf[mu]; e.ld = X->leaf_ld[mu];
+      e.rows = rows[t]; e.expo = expo[t];
+      lv.push_back(e);
+    }
+    Op g; g.kind = OP_EGATHER; g.toff = put(P, lv); g.count = (int)lv.size(); g.c[0] = mc;
+    g.p0 = const_cast<int32_t*>(idx + c0 * d); g.i0 = d;
+    P.ops.push_back(g);
+    Op nrm; nrm.kind = OP_ENORM; nrm.toff = g.toff; nrm.count = g.count; nrm.c[0] = mc;
+    P.ops.push_back(nrm);
+    for (int h = 1; h <= H; ++h) {
+      std::vector<GemmDesc> ds;
+      std::vector<EntryNode> en;
+      for (int t = 0; t < nn; ++t) {
+        if (tr.is_leaf(t) || tr.height[t] != h) continue;
+        const int s1 = tr.son1[t], s2 = tr.son2[t];
+        const int k1 = X->rank[s1], k2 = X->rank[s2], kt = t == 0 ? 1 : X->rank[t];
+        GemmDesc q = blank_desc();
+        q.kr = 1; q.krK2 = k2; q.krY1 = rows[s1]; q.krY2 = rows[s2]; q.krld1 = k1; q.krld2 = k2;
+        q.A = rows[s1]; q.sAm = 0; q.sAk = 1;
+        q.B = X->transfer[t]; q.sBk = 1; q.sBn = (int64_t)k1 * k2;
+        q.C = rows[t]; q.sCm = kt; q.sCn = 1;
+        q.M = (int)mc; q.N = kt; q.K = k1 * k2;
+        ds.push_back(q);
+        EntryNode e;
+        std::memset(&e, 0, sizeof(e));
+        e.k = kt; e.rows = rows[t]; e.expo = expo[t]; e.expo1 = expo[s1]; e.expo2 = expo[s2];
+        en.push_back(e);
+      }
+      if (ds.empty()) continue;
+      // the root matrix is float64; inner transfer tensors have transfer_dtype
+      std::vector<GemmDesc> dr, di;
+      for (auto& q : ds) (q.N == 1 && q.B == X->transfer[0] ? dr : di).push_back(q);
+      add_gemm(P, di, F64, X->transfer_dtype, F64, MATH_F64, GEMM_STORE, true, true);
+      add_gemm(P, dr, F64, F64, F64, MATH_F64, GEMM_STORE, true, true);
+      Op n2; n2.kind = OP_ENORM; n2.toff = put(P, en); n2.count = (int)en.size(); n2.c[0] = mc;
+      P.ops.push_back(n2);
+    }
+    Op f; f.kind = OP_EFINISH; f.p0 = rows[0]; f.p1 = expo[0]; f.p2 = out + c0; f.c[0] = mc;
+    f.scale0 = X->log2_scale;
+    P.ops.push_back(f);
+  }
+  return HT_OK;
+}
+
+ht_status ht_entries_workspace(ht_context* ctx, const ht_desc* X, int64_t m, size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(HT_EINVAL, "NULL argument");
+  if (m < 0) return fail(HT_EINVAL, "m must be >= 0");
+  ht_status s = check_desc(X, "X", false);
+  if (s) return s;
+  Plan P;
+  return build_entries(X, m, nullptr, nullptr, nullptr, P, bytes);
+}
+
+ht_status ht_entries(ht_context* ctx, const ht_desc* X, int64_t m, const int32_t* idx, double* out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  ht_status st = ht_entries_workspace(ctx, X, m, &need);
+  if (st) return st;
+  st = check_desc(X, "X");
+  if (st) return st;
+  if (m == 0) return HT_OK;
+  if (!idx || !out) return fail(HT_EINVAL, "idx or out is NULL");
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_entries(X, m, idx, out, ws, P, nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ sum (Lemma (sum))
+ht_status ht_add(ht_context* ctx, double alpha, const ht_desc* A, double beta, const ht_desc* C, const ht_desc* S,
+                 int64_t* out_log2_scale, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  ht_status st = check_desc(A, "A");
+  if (st) return st;
+  st = check_desc(C, "C");
+  if (st) return st;
+  st = check_desc(S, "S");
+  if (st) return st;
+  if (A->d != C->d || A->d != S->d) return fail(HT_ESHAPE, "d differs");
+  const int d = A->d;
+  Tree tr(d);
+  for (int mu = 0; mu < d; ++mu)
+    if (A->n[mu] != C->n[mu] || A->n[mu] != S->n[mu]) return fail(HT_ESHAPE, "n differs");
+  for (int t = 1; t < tr.nn; ++t)
+    if (S->rank[t] != A->rank[t] + C->rank[t]) return fail(HT_ESHAPE, "S ranks must be rank_A + rank_C");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(HT_EINVAL, "alpha and beta must be finite");
+  const long long s = std::max<long long>(A->log2_scale, C->log2_scale);
+  const double a = std::ldexp(alpha, (int)std::max<long long>(-2000, A->log2_scale - s));
+  const double c = std::ldexp(beta, (int)std::max<long long>(-2000, C->log2_scale - s));
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  for (int mu = 0; mu < d; ++mu) {
+    const int t = tr.leaf_node[mu];
+    const int64_t n = A->n[mu];
+    const int ka = A->rank[t], kc = C->rank[t];
+    add_copy(P, A->leaf[mu], A->frame_dtype, S->leaf[mu], S->frame_dtype, ka, n, A->leaf_ld[mu], 1,
+             S->leaf_ld[mu], 1, 1.0);
+    add_copy(P, C->leaf[mu], C->frame_dtype, (char*)S->leaf[mu] + (size_t)ka * S->leaf_ld[mu] * esize(S->frame_dtype),
+             S->frame_dtype, kc, n, C->leaf_ld[mu], 1, S->leaf_ld[mu], 1, 1.0);
+  }
+  for (int t = 0; t < tr.nn; ++t) {
+    if (tr.is_leaf(t)) continue;
+    const int s1 = tr.son1[t], s2 = tr.son2[t];
+    const int K1 = S->rank[s1], K2 = S->rank[s2], Kt = t == 0 ? 1 : S->rank[t];
+    const int sdt = t == 0 ? HT_F64 : S->transfer_dtype;
+    const int adt = t == 0 ? HT_F64 : A->transfer_dtype, cdt = t == 0 ? HT_F64 : C->transfer_dtype;
+    add_fill(P, S->transfer[t], (size_t)Kt * K1 * K2 * esize(sdt));
+    const int at = t == 0 ? 1 : A->rank[t], a1 = A->rank[s1], a2 = A->rank[s2];
+    const int ct = t == 0 ? 1 : C->rank[t], c1 = C->rank[s1], c2 = C->rank[s2];
+    add_copy3(P, A->transfer[t], adt, S->transfer[t], sdt, at, a1, a2, (int64_t)a1 * a2, a2, 1, (int64_t)K1 * K2, K2, 1,
+              t == 0 ? a : 1.0);
+    const size_t off = t == 0 ? (size_t)a1 * K2 + a2 : ((size_t)at * K1 * K2 + (size_t)a1 * K2 + a2);
+    add_copy3(P, C->transfer[t], cdt, (char*)S->transfer[t] + off * esize(sdt), sdt, ct, c1, c2, (int64_t)c1 * c2, c2, 1,
+              (int64_t)K1 * K2, K2, 1, t == 0 ? c : 1.0);
+  }
+  if (out_log2_scale) *out_log2_scale = s;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ================================================================== bounds validation (host only)
+// Builds a plan against fake, disjoint address ranges sized from the shapes
+// (user buffers and every workspace allocation) and checks that every byte a
+// kernel of the plan may touch lies inside one of them.
+namespace {
+
+struct FakeSpace {
+  uintptr_t next = (uintptr_t)1 << 40;
+  void* get(size_t bytes, const std::string& what) {
+    next = (next + 4095) & ~(uintptr_t)4095;
+    void* p = reinterpret_cast<void*>(next);
+    reg(p, bytes, what);
+    next += bytes + 4096;  // a gap: an overrun never lands in the neighbour
+    return p;
+  }
+};
+
+struct FakeTensor {
+  std::vector<int64_t> n, ld;
+  std::vector<int32_t> rank;
+  std::vector<void*> leaf, transfer;
+  ht_desc desc;
+};
+
+void fake_tensor(FakeSpace& F, const ht_desc* X, const std::vector<int>& ranks, int fdt, int tdt, FakeTensor& T,
+                 const std::string& name) {
+  const int d = X->d;
+  Tree tr(d);
+  T.n.assign(X->n, X->n + d);
+  T.ld = T.n;
+  T.rank.assign(ranks.begin(), ranks.end());
+  T.leaf.assign(d, nullptr);
+  T.transfer.assign(tr.nn, nullptr);
+  for (int mu = 0; mu < d; ++mu)
+    T.leaf[mu] = F.get((size_t)T.n[mu] * ranks[tr.leaf_node[mu]] * esize(fdt), name + " leaf");
+  for (int t = 0; t < tr.nn; ++t) {
+    if (tr.is_leaf(t)) continue;
+    const int kt = t == 0 ? 1 : ranks[t];
+    T.transfer[t] = F.get((size_t)kt * ranks[tr.son1[t]] * ranks[tr.son2[t]] * esize(t == 0 ? F64 : tdt),
+                          name + " transfer");
+  }
+  T.desc = *X;
+  T.desc.n = T.n.data();
+  T.desc.rank = T.rank.data();
+  T.desc.frame_dtype = fdt;
+  T.desc.transfer_dtype = tdt;
+  T.desc.leaf = T.leaf.data();
+  T.desc.leaf_ld = T.ld.data();
+  T.desc.transfer = T.transfer.data();
+}
+
+bool inside(uintptr_t lo, uintptr_t hi, std::string* where) {
+  for (const auto& r : *g_regions)
+    if (lo >= r.lo && hi <= r.lo + r.bytes) { *where = r.what; return true; }
+  return false;
+}
+
+ht_status check_range(const void* base, int64_t lo_el, int64_t hi_el, int esz, const std::string& what) {
+  if (!base) return fail(HT_EINVAL, "validator: NULL pointer in " + what);
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t lo = b + (uintptr_t)(lo_el * esz), hi = b + (uintptr_t)((hi_el + 1) * esz);
+  std::string where;
+  if (!inside(lo, hi, &where)) return fail(HT_EINVAL, "validator: out-of-bounds access in " + what);
+  return HT_OK;
+}
+
+ht_status validate_plan(const Plan& P, int64_t m_entries) {
+  auto at = [&](size_t off) { return P.table.data() + off; };
+  int opi = 0;
+  for (const auto& op : P.ops) {
+    const std::string tag = "op " + std::to_string(opi++) + " kind " + std::to_string(op.kind);
+    ht_status s = HT_OK;
+    if (op.kind == OP_GEMM) {
+      const GemmDesc* ds = reinterpret_cast<const GemmDesc*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const GemmDesc& g = ds[i];
+        if (g.M <= 0 || g.N <= 0) continue;
+        const int ea = esize(op.g.tA), eb = esize(op.g.tB), ec = esize(op.g.tC);
+        const int nseg = g.nseg > 0 ? g.nseg : g.KB;
+        const std::string w = tag + " desc " + std::to_string(i);
+        if (g.nbatch > op.g.maxbatch) return fail(HT_EINVAL, "validator: batch " + w);
+        if (((g.M + 63) / 64) * ((g.N + 63) / 64) > op.g.maxtiles) return fail(HT_EINVAL, "validator: tiles " + w);
+        for (int sg = 0; sg < nseg; ++sg) {
+          const int ks = g.nseg > 0 ? g.segK[sg] : g.K;
+          if (ks <= 0) continue;
+          const int64_t bat = (int64_t)(g.nbatch - 1);
+          if (g.kr) {
+            s = check_range(g.krY1, 0, (int64_t)(g.M - 1) * g.krld1 + (ks - 1) / g.krK2, 8, w + " KR1");
+            if (!s) s = check_range(g.krY2, 0, (int64_t)(g.M - 1) * g.krld2 + std::min(ks, g.krK2) - 1, 8, w + " KR2");
+          } else {
+            const void* Ab = g.nseg > 0 ? g.segA[sg] : g.A;
+            const int64_t a0 = g.nseg > 0 ? 0 : (int64_t)sg * g.sAkb;
+            const int64_t sak = g.nseg > 0 ? g.segAk[sg] : g.sAk;
+            s = check_range(Ab, a0, a0 + (int64_t)(g.M - 1) * g.sAm + (int64_t)(ks - 1) * sak + bat * g.sAb, ea, w + " A");
+          }
+          if (s) return s;
+          const int64_t b0 = g.nseg > 0 ? g.segBoff[sg] : (int64_t)sg * g.sBkb;
+          s = check_range(g.B, b0, b0 + (int64_t)(ks - 1) * g.sBk + (int64_t)(g.N - 1) * g.sBn + bat * g.sBb, eb,
+                          w + " B");
+          if (s) return s;
+        }
+        s = check_range(g.C, 0, (int64_t)(g.M - 1) * g.sCm + (int64_t)(g.N - 1) * g.sCn + (int64_t)(g.nbatch - 1) * g.sCb,
+                        ec, w + " C");
+        if (s) return s;
+        if (g.alpha_dev) { s = check_range(g.alpha_dev, 0, 0, 8, w + " alpha"); if (s) return s; }
+      }
+    } else if (op.kind == OP_CHOL1 || op.kind == OP_CHOL2 || op.kind == OP_EIG || op.kind == OP_RANK ||
+               op.kind == OP_PROJPREP || op.kind == OP_SIGMA) {
+      const SmallArgs* as = reinterpret_cast<const SmallArgs*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const SmallArgs& a = as[i];
+        const int64_t kk = (int64_t)a.K * a.K;
+        const std::string w = tag + " node " + std::to_string(a.node);
+        if (a.K < 1 || a.K > KMAX) return fail(HT_EINVAL, "validator: K " + w);
+        auto chk = [&](const void* p, int64_t n, int e, const char* nm) -> ht_status {
+          return check_range(p, 0, n - 1, e, w + " " + nm);
+        };
+        if (op.kind == OP_CHOL1 || op.kind == OP_CHOL2) {
+          if ((s = chk(a.G, kk, 8, "G")) || (s = chk(a.G2, kk, 8, "G2")) || (s = chk(a.R1, kk, 8, "R1")) ||
+              (s = chk(a.Ri1, kk, 8, "Ri1")))
+            return s;
+          if (op.kind == OP_CHOL2 && ((s = chk(a.R, kk, 8, "R")) || (s = chk(a.Ri, kk, 8, "Ri")) ||
+                                      (s = chk(a.Rf, kk, esize(a.rf_type), "Rf"))))
+            return s;
+        } else if (op.kind == OP_EIG) {
+          if ((s = chk(a.Bh, kk, 8, "Bh")) || (s = chk(a.Q, kk, 8, "Q")) || (s = chk(a.lam, a.K, 8, "lam")) ||
+              (s = chk(a.scratch, 2 * kk + (int64_t)(a.K + (a.K & 1) - 1) * (a.K + (a.K & 1)), 8, "scratch")))
+            return s;
+        } else if (op.kind == OP_RANK) {
+          if ((s = chk(a.lam, a.K, 8, "lam")) || (s = chk(a.rank_dev, 1, 4, "rank"))) return s;
+        } else if (op.kind == OP_PROJPREP) {
+          if ((s = chk(a.Q, kk, 8, "Q")) || (s = chk(a.rank_dev, 1, 4, "rank")) || (s = chk(a.lam, a.K, 8, "lam")))
+            return s;
+          if (a.Qm && (s = chk(a.Qm, (int64_t)a.K * a.rcap, 8, "Qm"))) return s;
+          if (a.QmT && (s = chk(a.QmT, (int64_t)a.K * a.rcap, esize(a.rf_type), "QmT"))) return s;
+          if (a.sigma_out && (s = chk(a.sigma_out, KMAX, 8, "sigma"))) return s;
+          if (a.rcap < 1 || a.rcap > a.K) return fail(HT_EINVAL, "validator: rcap " + w);
+        } else if (op.kind == OP_SIGMA) {
+          if ((s = chk(a.lam, a.K, 8, "lam"))) return s;
+        }
+      }
+    } else if (op.kind == OP_FILL) {
+      if ((s = check_range(op.p0, 0, (int64_t)op.bytes / 4 - 1, 4, tag + " fill"))) return s;
+    } else if (op.kind == OP_COPY) {
+      const int64_t n0 = op.c[0], n1 = op.c[1], n2 = op.c[2];
+      if (n0 * n1 * n2 == 0) continue;
+      if ((s = check_range(op.p0, 0, (n0 - 1) * op.c[3] + (n1 - 1) * op.c[4] + (n2 - 1) * op.c[5], esize(op.i0),
+                           tag + " copy src")))
+        return s;
+      if ((s = check_range(op.p1, 0, (n0 - 1) * op.c[6] + (n1 - 1) * op.c[7] + (n2 - 1) * op.c[8], esize(op.i1),
+                           tag + " copy dst")))
+        return s;
+    } else if (op.kind == OP_EGATHER || op.kind == OP_ENORM) {
+      const EntryNode* en = reinterpret_cast<const EntryNode*>(at(op.toff));
+      const int64_t mc = op.c[0];
+      for (int i = 0; i < op.count; ++i) {
+        const std::string w = tag + " entry node " + std::to_string(i);
+        if ((s = check_range(en[i].rows, 0, mc * en[i].k - 1, 8, w + " rows")) ||
+            (s = check_range(en[i].expo, 0, mc - 1, 4, w + " expo")))
+          return s;
+        if (op.kind == OP_EGATHER) {
+          if ((s = check_range(op.p0, 0, mc * op.i0 - 1, 4, w + " idx"))) return s;
+        }
+        if (en[i].expo1 && (s = check_range(en[i].expo1, 0, mc - 1, 4, w + " expo1"))) return s;
+        if (en[i].expo2 && (s = check_range(en[i].expo2, 0, mc - 1, 4, w + " expo2"))) return s;
+      }
+    } else if (op.kind == OP_EFINISH) {
+      if ((s = check_range(op.p0, 0, op.c[0] - 1, 8, tag + " vals")) || (s = check_range(op.p1, 0, op.c[0] - 1, 4, tag + " expo")) ||
+          (s = check_range(op.p2, 0, op.c[0] - 1, 8, tag + " out")))
+        return s;
+    } else if (op.kind == OP_ROOTNORM) {
+      if ((s = check_range(op.p1, 0, (int64_t)op.i0 * op.i1 - 1, 8, tag + " root"))) return s;
+    }
+  }
+  (void)m_entries;
+  return HT_OK;
+}
+
+struct RegionScope {
+  std::vector<Region> regions;
+  RegionScope() { g_regions = &regions; }
+  ~RegionScope() { g_regions = nullptr; }
+};
+
+}  // namespace
+
+extern "C" {
+
+ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_truncate_workspace(nullptr, X, n_in, opts, &need);
+  if (st) return st;
+  FakeSpace F;
+  std::vector<FakeTensor> fx(n_in);
+  std::vector<ht_desc> xs(n_in);
+  const int d = X[0].d;
+  Tree tr(d);
+  for (int c = 0; c < n_in; ++c) {
+    std::vector<int> rk(X[c].rank, X[c].rank + tr.nn);
+    fake_tensor(F, &X[c], rk, X[c].frame_dtype, X[c].transfer_dtype, fx[c], "X");
+    xs[c] = fx[c].desc;
+  }
+  SumInfo S;
+  if ((st = sum_info(xs.data(), nullptr, n_in, S))) return st;
+  std::vector<int> rc(tr.nn, 1);
+  for (int t = 1; t < tr.nn; ++t)
+    rc[t] = opts->mode == HT_RANK_FIXED ? std::min(opts->ranks[t], S.K[t])
+                                        : (opts->max_rank > 0 ? std::min(opts->max_rank, S.K[t]) : S.K[t]);
+  if (opts->mode == HT_RANK_TOL) rc[tr.son1[0]] = rc[tr.son2[0]] = std::min(rc[tr.son1[0]], rc[tr.son2[0]]);
+  FakeTensor fo;
+  const int T = opts->precision == HT_PREC_MIXED ? HT_F32 : HT_F64;
+  fake_tensor(F, &X[0], rc, T, T, fo, "out");
+  void* ranks = F.get((size_t)tr.nn * 4, "out_ranks");
+  void* scale = F.get(8, "out_scale");
+  void* flags = F.get(4, "flags");
+  void* sigma = F.get((size_t)tr.nn * KMAX * 8, "sigma");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();  // only the individual workspace allocations count
+  Plan P;
+  std::vector<double> coef(n_in, 1.0);
+  st = build_truncate(nullptr, xs.data(), coef.data(), n_in, opts, &fo.desc, (int32_t*)ranks, (int64_t*)scale,
+                      (uint32_t*)flags, (double*)sigma, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_orthogonalize_workspace(nullptr, X, precision, &need);
+  if (st) return st;
+  FakeSpace F;
+  Tree tr(X->d);
+  FakeTensor fx;
+  std::vector<int> rk(X->rank, X->rank + tr.nn);
+  fake_tensor(F, X, rk, X->frame_dtype, X->transfer_dtype, fx, "X");
+  void* scale = F.get(8, "scale");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  Plan P;
+  st = build_orth(&fx.desc, precision, (int64_t*)scale, nullptr, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_gramians(const ht_desc* X) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_gramians_workspace(nullptr, X, &need);
+  if (st) return st;
+  FakeSpace F;
+  Tree tr(X->d);
+  FakeTensor fx;
+  std::vector<int> rk(X->rank, X->rank + tr.nn);
+  fake_tensor(F, X, rk, X->frame_dtype, X->transfer_dtype, fx, "X");
+  std::vector<double*> bh(tr.nn, nullptr), sg(tr.nn, nullptr);
+  for (int t = 1; t < tr.nn; ++t) {
+    bh[t] = (double*)F.get((size_t)rk[t] * rk[t] * 8, "bhat");
+    sg[t] = (double*)F.get((size_t)rk[t] * 8, "sigma");
+  }
+  void* units = F.get(8, "units");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  Plan P;
+  st = build_gram(&fx.desc, bh.data(), sg.data(), (int64_t*)units, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_entries_workspace(nullptr, X, m, &need);
+  if (st) return st;
+  FakeSpace F;
+  Tree tr(X->d);
+  FakeTensor fx;
+  std::vector<int> rk(X->rank, X->rank + tr.nn);
+  fake_tensor(F, X, rk, X->frame_dtype, X->transfer_dtype, fx, "X");
+  void* idx = F.get((size_t)m * X->d * 4, "idx");
+  void* out = F.get((size_t)m * 8, "out");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  Plan P;
+  st = build_entries(&fx.desc, m, (const int32_t*)idx, (double*)out, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, m);
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Strided, batched, segmented GEMM on the gfx950 matrix cores.
+//
+// Every contraction of the truncation is one of these: frame Grams U^T U,
+// mode-1/2/3 products (X,Y,Z) o B on row-major transfer tensors, the Gramian
+// contractions of eqs. (acctransferSon1/2) and the projections of
+// eq. (transfertransformationtrunc).  A 64x64 output tile per workgroup of four
+// wave64s (each wave owns 32x32 = 2x2 MFMA 16x16 blocks); the reduction is
+// staged through LDS in k-slabs of 16 with a register prefetch of the next
+// slab.  Operands are converted to the MFMA type when they are written to LDS,
+// so float32 data feeds the FP64 matrix cores exactly.
+#include "ht_internal.h"
+
+namespace ht {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+template <typename T> struct AccOf;
+template <> struct AccOf<float> { using V = floatx4; };
+template <> struct AccOf<double> { using V = doublex4; };
+
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Reduction cursor over segments / reduction blocks.
+struct Cursor {
+  int seg;   // current segment
+  int k0;    // offset inside the segment
+};
+
+template <typename TA, typename TB, typename TM>
+__global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ descs, int maxbatch,
+                                                  int splitk, int tC, int mode, int aK, int bK) {
+  __shared__ TM As[BK][BM + 4];
+  __shared__ TM Bs[BK][BN + 4];
+
+  const GemmDesc& D = descs[blockIdx.z / maxbatch];
+  const int b = blockIdx.z % maxbatch;
+  if (b >= D.nbatch) return;
+  const int M = D.M, N = D.N;
+  const int tilesN = (N + BN - 1) / BN;
+  const int tilesM = (M + BM - 1) / BM;
+  if ((int)blockIdx.x >= tilesM * tilesN) return;
+  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+
+  const int nseg = D.nseg > 0 ? D.nseg : D.KB;
+  auto segK = [&](int s) -> int { return D.nseg > 0 ? D.segK[s] : D.K; };
+  int total = 0;
+  for (int s = 0; s < nseg; ++s) total += (segK(s) + BK - 1) / BK;
+  const int per = (total + splitk - 1) / splitk;
+  const int t0 = blockIdx.y * per;
+  const int t1 = min(total, t0 + per);
+  if (t0 >= t1 && !(mode == GEMM_STORE && blockIdx.y == 0)) return;
+
+  const TA* Ab = reinterpret_cast<const TA*>(D.A);
+  const TB* Bb = reinterpret_cast<const TB*>(D.B);
+  const int64_t aoff_b = (int64_t)b * D.sAb, boff_b = (int64_t)b * D.sBb;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // thread -> (row, k) coordinates of its four loaded elements
+  int a_r[4], a_k[4], b_c[4], b_k[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (aK) { a_r[i] = tid >> 2; a_k[i] = (tid & 3) * 4 + i; }
+    else    { a_r[i] = (tid & 15) * 4 + i; a_k[i] = tid >> 4; }
+    if (bK) { b_c[i] = tid >> 2; b_k[i] = (tid & 3) * 4 + i; }
+    else    { b_c[i] = (tid & 15) * 4 + i; b_k[i] = tid >> 4; }
+  }
+
+  // locate tile t0
+  Cursor cur{0, 0};
+  {
+    int skip = t0;
+    while (cur.seg < nseg) {
+      int nt = (segK(cur.seg) + BK - 1) / BK;
+      if (skip < nt) { cur.k0 = skip * BK; break; }
+      skip -= nt;
+      cur.seg++;
+    }
+  }
+
+  TM ra[4], rb[4];
+  auto load = [&](const Cursor& c) {
+    const int s = c.seg;
+    const int ks = segK(s);
+    const TA* Ap = (D.nseg > 0 ? reinterpret_cast<const TA*>(D.segA[s]) : Ab + (int64_t)s * D.sAkb) + aoff_b;
+    const TB* Bp = Bb + (D.nseg > 0 ? D.segBoff[s] : (int64_t)s * D.sBkb) + boff_b;
+    const int64_t sAk = D.nseg > 0 ? D.segAk[s] : D.sAk;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gm = tm * BM + a_r[i], gk = c.k0 + a_k[i];
+      if (D.kr) {
+        ra[i] = (gm < M && gk < ks)
+                    ? (TM)(D.krY1[(int64_t)gm * D.krld1 + gk / D.krK2] * D.krY2[(int64_t)gm * D.krld2 + gk % D.krK2])
+                    : (TM)0;
+      } else {
+        ra[i] = (gm < M && gk < ks) ? (TM)Ap[(int64_t)gm * D.sAm + (int64_t)gk * sAk] : (TM)0;
+      }
+      const int gn = tn * BN + b_c[i], gkb = c.k0 + b_k[i];
+      rb[i] = (gn < N && gkb < ks) ? (TM)Bp[(int64_t)gkb * D.sBk + (int64_t)gn * D.sBn] : (TM)0;
+    }
+  };
+  auto advance = [&](Cursor& c) {
+    c.k0 += BK;
+    if (c.k0 >= segK(c.seg)) { c.seg++; c.k0 = 0; }
+    while (c.seg < nseg && segK(c.seg) == 0) c.seg++;
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      As[a_k[i]][a_r[i]] = ra[i];
+      Bs[b_k[i]][b_c[i]] = rb[i];
+    }
+  };
+
+  using V = typename AccOf<TM>::V;
+  V acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = V{0, 0, 0, 0};
+
+  if (t0 < t1) {
+    load(cur);
+    stash();
+    __syncthreads();
+    for (int it = t0; it < t1; ++it) {
+      const bool more = it + 1 < t1;
+      if (more) { advance(cur); load(cur); }
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        const TM a0 = As[kr][wm * 32 + (lane & 15)];
+        const TM a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+        const TM b0 = Bs[kr][wn * 32 + (lane & 15)];
+        const TM b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      }
+      __syncthreads();
+      if (more) {
+        stash();
+        __syncthreads();
+      }
+    }
+  }
+
+  double alpha = D.alpha;
+  if (D.alpha_dev) alpha *= *D.alpha_dev;
+  char* Cb = reinterpret_cast<char*>(D.C);
+  const int esz = tC == F64 ? 8 : 4;
+  const int64_t coff_b = (int64_t)b * D.sCb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // accumulator register v of lane l: FP32 16x16x4 holds rows 4(l/16)+v,
+        // FP64 16x16x4 holds rows 4v + l/16 (both in column l%16)
+        const int rin = sizeof(TM) == 8 ? v * 4 + (lane >> 4) : (lane >> 4) * 4 + v;
+        const int row = tm * BM + wm * 32 + i * 16 + rin;
+        const int col = tn * BN + wn * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          const double val = alpha * (double)acc[i][j][v];
+          const int64_t off = coff_b + (int64_t)row * D.sCm + (int64_t)col * D.sCn;
+          if (tC == F64) {
+            double* p = reinterpret_cast<double*>(Cb) + off;
+            if (mode == GEMM_ATOMIC) atomicAdd(p, val); else *p = val;
+          } else {
+            float* p = reinterpret_cast<float*>(Cb) + off;
+            if (mode == GEMM_ATOMIC) atomicAdd(p, (float)val); else *p = (float)val;
+          }
+        }
+      }
+  (void)esz;
+}
+
+template <typename TA, typename TB, typename TM>
+hipError_t go(const GemmLaunch& g, hipStream_t s) {
+  dim3 grid(g.maxtiles, g.splitk, g.ndesc * g.maxbatch);
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TM>), grid, dim3(NT), 0, s, g.descs, g.maxbatch, g.splitk,
+                     g.tC, g.mode, g.a_kcontig ? 1 : 0, g.b_kcontig ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s) {
+  if (g.ndesc <= 0 || g.maxtiles <= 0) return hipSuccess;
+  const bool a32 = g.tA == F32, b32 = g.tB == F32;
+  if (g.math == MATH_F32) {
+    if (a32 && b32) return go<float, float, float>(g, s);
+    if (a32 && !b32) return go<float, double, float>(g, s);
+    if (!a32 && b32) return go<double, float, float>(g, s);
+    return go<double, double, float>(g, s);
+  }
+  if (a32 && b32) return go<float, float, double>(g, s);
+  if (a32 && !b32) return go<float, double, double>(g, s);
+  if (!a32 && b32) return go<double, float, double>(g, s);
+  return go<double, double, double>(g, s);
+}
+
+}  // namespace ht

@@ -1,0 +1,152 @@
+// Internal declarations of the HT hierarchical-SVD library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ht {
+
+// Largest sum rank the LDS-resident small dense kernels accept.
+constexpr int KMAX = 128;
+// Segments of a segmented reduction (one per summand of a lazy sum).
+constexpr int MAX_SEG = 8;
+
+// Element types of GEMM operands / results.
+enum DType : int { F64 = 0, F32 = 1 };
+
+// One strided (batched) GEMM problem: C(m,n) (op)= alpha * sum_r A(m,r) B(r,n).
+//   A(m,k) = A[m*sAm + k*sAk], B(k,n) = B[k*sBk + n*sBn], C(m,n) = C[m*sCm + n*sCn].
+// The reduction index r runs over KB blocks of K (block kb shifts A by kb*sAkb and
+// B by kb*sBkb) or, if nseg > 0, over nseg segments with their own A base,
+// B offset and length.  nbatch independent problems differ by sAb/sBb/sCb.
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t sAm, sAk, sBk, sBn, sCm, sCn;
+  int64_t sAb, sBb, sCb;
+  int64_t sAkb, sBkb;
+  int32_t M, N, K, KB;
+  int32_t nbatch, nseg;
+  const void* segA[MAX_SEG];
+  int64_t segBoff[MAX_SEG];
+  int32_t segK[MAX_SEG];
+  int64_t segAk[MAX_SEG];   // per-segment k-stride of A
+  // Khatri-Rao operand (entry evaluation, eq. (transfermult)): if kr != 0,
+  // A(m,k) = krY1[m*krld1 + k / krK2] * krY2[m*krld2 + k % krK2] (float64 rows).
+  int32_t kr, krK2;
+  const double* krY1;
+  const double* krY2;
+  int64_t krld1, krld2;
+  double alpha;
+  const double* alpha_dev;  // if set, alpha is multiplied by *alpha_dev
+};
+
+// How a GEMM writes C.
+enum GemmMode : int { GEMM_STORE = 0, GEMM_ATOMIC = 1 };
+// Which matrix cores: FP32 MFMA (float accumulate) or FP64 MFMA.
+enum GemmMath : int { MATH_F32 = 0, MATH_F64 = 1 };
+
+struct GemmLaunch {
+  int tA, tB, tC;          // DType of A, B, C
+  int math;                // GemmMath
+  int mode;                // GemmMode
+  bool a_kcontig;          // sAk == 1 (else sAm == 1)
+  bool b_kcontig;          // sBk == 1 (else sBn == 1)
+  int splitk;              // blocks along the reduction (GEMM_ATOMIC if > 1)
+  int ndesc, maxbatch, maxtiles;
+  const GemmDesc* descs;   // device pointer
+};
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t stream);
+
+// ---------------------------------------------------------------- small dense kernels
+// Per-node argument block of the small dense kernels (device-resident table).
+struct SmallArgs {
+  int32_t K;               // matrix order
+  int32_t node;            // preorder node id
+  int32_t rcap;            // projection width (output rank bound)
+  int32_t rfix;            // fixed rank (>0) or 0 = read from rank_dev
+  double* G;               // K x K Gram (input)
+  double* G2;              // K x K second-sweep Gram
+  double* R1;              // K x K first-sweep factor
+  double* Ri1;             // K x K inverse of the first-sweep factor
+  double* R;               // K x K upper factor (output, normalised by 2^-e)
+  double* Ri;              // K x K inverse of the unnormalised factor
+  double tol_rel;          // pivot tolerance relative to the largest diagonal entry
+  void* Rf;                // K x K copy of R in the forward-product type
+  int32_t rf_type;         // DType of Rf
+  int32_t clamp_only;      // 1: first sweep (clamp tiny pivots), 0: final
+  double* Q;               // K x K eigenvectors (columns, descending)
+  double* lam;             // K eigenvalues (descending, >= 0)
+  double* Qm;              // K x rcap masked leading eigenvectors
+  void* QmT;               // rcap x K transpose in the forward type
+  int32_t* rank_dev;       // rank of this node (device)
+  double* sigma_out;       // optional: 128 slots for sigma / ||A||
+  double* scratch;         // eigensolver scratch, 3 K^2 doubles
+  double* Bh;              // K x K Gramian (eigensolver input)
+};
+
+struct GlobalState {       // device-resident per-call scalars
+  long long log2_scale;    // running scale exponent
+  unsigned int flags;
+  int pad;
+  double alpha_gram;       // 2^(-2 e_D)
+  long long e_D;           // binary exponent of ||B_D||_F
+  double norm2_units;      // ||A||^2 in Gramian units (trace of Bhat_t1)
+  double thr;              // tolerance threshold in Gramian units
+};
+
+hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);   // bytes: multiple of 4
+hipError_t launch_set_state(GlobalState* st, long long scale0, hipStream_t s);
+hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);
+hipError_t launch_eig(const SmallArgs* args, int n, double* scratch, hipStream_t s, GlobalState* st);
+hipError_t launch_rank_select(const SmallArgs* args, int n, int d, int mode, double eps, int rel,
+                              int max_rank, int t1, int t2, GlobalState* st, hipStream_t s);
+hipError_t launch_proj_prep(const SmallArgs* args, int n, const GlobalState* st, hipStream_t s);
+hipError_t launch_root_norm(const double* BD, int K1, int K2, GlobalState* st, hipStream_t s);
+hipError_t launch_copy_root(const double* src, int rows, int cols, int ld_src, double alpha,
+                            double* dst, int ld_dst, hipStream_t s);
+hipError_t launch_write_scale(const GlobalState* st, long long* out_scale, unsigned int* flags,
+                              int* root_rank, int add_eD, hipStream_t s);
+// dst[i*d0 + j*d1 + k*d2] = alpha * src[i*s0 + j*s1 + k*s2] over n0 x n1 x n2
+hipError_t launch_copy3(const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
+                        int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2,
+                        double alpha, hipStream_t s);
+hipError_t launch_sigma_from_lam(const SmallArgs* args, int n, double* const* sigma_ptrs,
+                                 hipStream_t s);
+
+// ---------------------------------------------------------------- entries (Section 3.1)
+struct EntryNode {
+  int32_t k;               // rank of the node (row length)
+  int32_t mode;            // leaves: 0-based mode
+  int32_t tdtype;          // DType of the leaf frame
+  int32_t pad;
+  const void* U;           // leaves: column-major frame
+  int64_t ld;              // leaves: leading dimension
+  double* rows;            // m x k rows of this node (normalised in place)
+  int32_t* expo;           // m binary exponents of this node
+  const int32_t* expo1;    // inner: son exponents (added)
+  const int32_t* expo2;
+};
+// leaves: rows[i][:] = U[idx[i][mode], :]; then every node: rows[i] /= 2^e_i.
+hipError_t launch_entry_gather(const EntryNode* nodes, int n, int64_t m, const int32_t* idx, int d,
+                               int maxk, hipStream_t s);
+hipError_t launch_entry_normalize(const EntryNode* nodes, int n, int64_t m, int maxk, hipStream_t s);
+// out[i] = rows_root[i] * 2^(expo_root[i] + log2_scale)
+hipError_t launch_entry_finish(const double* vals, const int32_t* expo, int64_t m, long long log2_scale,
+                               double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- tree (eq. (balanced))
+struct Tree {
+  int d = 0, nn = 0;
+  std::vector<int> parent, son1, son2, lo, hi, depth, height, leaf_node;
+  explicit Tree(int d_);
+  bool is_leaf(int t) const { return son1[t] < 0; }
+  int mode(int t) const { return lo[t]; }
+  int max_depth() const;
+};
+
+}  // namespace ht
