@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of truncating an HT sum by the hierarchical SVD on one MI355X.
+
+Workload (the paper's runtime tests use random H-tensors with n = 10 000 and
+d up to 64): two seeded HT tensors with d = 64, n = 10 000, k = 64 (float32
+N(0,1) leaf frames, transfer tensors with singular values 0.9^i), summed
+lazily (sum rank 128) and truncated to relative accuracy 1e-6 by
+ht_truncate: CholeskyQR2 orthogonalisation bottom-up, reduced Gramians
+top-down, eigen-decompositions, rank selection and projection.  A "step" is
+one such sum-truncation with all inputs resident in HBM.
+
+Prints one JSON line (stdout).  The mixed-precision path is the headline
+value; the float64 path and the fixed-rank (r = 64) reading are timed beside
+it.  `roofline` describes the kernel with the largest share of the timed
+region (HIP events around every launch, on the library's stream);
+`cpu_baseline` times the float64 NumPy oracle on one sum-truncation of the
+same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {"double": 78.6e12, "float": 157.3e12}   # MI355X dense MFMA peaks, FP64 / FP32
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(cfg):
+    """One sum-truncation of the same workload by the float64 oracle."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import htsynth as S
+    from oracle import ht_oracle as O
+    a, c = S.config_pair(3)
+    A, C = O.from_input(a), O.from_input(c)
+    t0 = time.perf_counter()
+    X = O.add(A, C)
+    O.truncate(X, mode="tol", eps=cfg["eps"], relative=True)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return dict(value=1.0 / dt, unit="sum-truncations/s", cores=int(threads), kind="oracle",
+                sample=f"one full sum-truncation of the same workload (d=64, n=1e4, k=64+64, rel. tol "
+                       f"{cfg['eps']:g}) by the float64 NumPy oracle, {dt:.1f} s wall clock")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--breakdown", action="store_true", help="print the per-step profile to stderr")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the truncation of one HT sum per GPU "
+              "and has no multi-GPU path (see the sharding notes in DESIGN.md); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1708_03340_amd as H
+    import htsynth as S
+
+    cfg = dict(d=64, n=10000, k=64, eps=1e-6)
+    torch.cuda.set_device(0)
+    log("bench: generating inputs (d=64, n=1e4, k=64, float32)")
+    a, c = S.config_pair(3)
+    A, C = H.DeviceHT.from_input(a), H.DeviceHT.from_input(c)
+    torch.cuda.synchronize()
+    mixed = H.Truncator([A, C], [1.0, 1.0], mode=H.HT_RANK_TOL, eps=cfg["eps"], relative=True,
+                        precision=H.HT_PREC_MIXED)
+    fp64 = H.Truncator([A, C], [1.0, 1.0], mode=H.HT_RANK_TOL, eps=cfg["eps"], relative=True,
+                       precision=H.HT_PREC_FP64, out_frame_dtype=torch.float32, out_transfer_dtype=torch.float32)
+    fixed = H.Truncator([A, C], [1.0, 1.0], mode=H.HT_RANK_FIXED, ranks=[64] * (2 * cfg["d"] - 1),
+                        precision=H.HT_PREC_MIXED)
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        res = mixed()
+    torch.cuda.synchronize()
+    ranks = res.ranks[1:]
+    log(f"bench: ranks chosen min {min(ranks)} max {max(ranks)} flags {res.flags & 255} "
+        f"max QL iterations {res.flags >> 8}")
+
+    # timed region: K mixed-precision sum-truncations, HIP events around every launch
+    H.profile_enable(True)
+    H.profile_reset()
+    log(f"bench: timing {args.steps} steps (mixed)")
+    t_mixed = timed(mixed, args.steps, torch)
+    prof = H.profile_read()
+    H.profile_enable(False)
+    H.profile_reset()
+    log(f"bench: mixed {t_mixed * 1e3:.3f} ms/step")
+
+    for _ in range(2):
+        fp64()
+    t_fp64 = timed(fp64, args.fp64_steps, torch)
+    log(f"bench: fp64 {t_fp64 * 1e3:.3f} ms/step")
+    for _ in range(2):
+        fixed()
+    t_fixed = timed(fixed, args.fp64_steps, torch)
+    log(f"bench: fixed r=64 (mixed) {t_fixed * 1e3:.3f} ms/step")
+
+    # dominant kernel of the timed region
+    by_kernel = {}
+    for e in prof:
+        k = by_kernel.setdefault(e["kernel"], dict(ms=0.0, flops=0.0, bytes=0.0, launches=0, labels=set()))
+        k["ms"] += e["ms"]; k["flops"] += e["flops"]; k["bytes"] += e["bytes"]; k["launches"] += e["launches"]
+        k["labels"].add(e["label"])
+    total_ms = sum(v["ms"] for v in by_kernel.values())
+    kname, kd = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
+    math_t = kname.rstrip(">").split(",")[-1] if kname.startswith("gemm") else None
+    if math_t in PEAKS:
+        achieved = kd["flops"] / (kd["ms"] * 1e-3)
+        roof = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAKS[math_t] / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAKS[math_t], traffic=None, kernel=kname,
+                    avg_launch_us=kd["ms"] * 1e3 / kd["launches"], launches_per_step=kd["launches"] / args.steps,
+                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps))
+    else:
+        achieved = kd["bytes"] / (kd["ms"] * 1e-3)
+        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / HBM_PEAK, traffic=None, kernel=kname,
+                    avg_launch_us=kd["ms"] * 1e3 / kd["launches"], launches_per_step=kd["launches"] / args.steps,
+                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps))
+    if args.breakdown or True:
+        labels = {}
+        for e in prof:
+            l = labels.setdefault(e["label"], [0.0, 0.0, 0])
+            l[0] += e["ms"]; l[1] += e["flops"]; l[2] += e["launches"]
+        log("bench: per-step breakdown (ms per sum-truncation, achieved TFLOP/s):")
+        for lab, (ms, fl, n) in sorted(labels.items(), key=lambda kv: -kv[1][0]):
+            log(f"  {lab:22s} {ms / args.steps:8.3f} ms  {fl / max(ms * 1e-3, 1e-12) / 1e12:7.2f} TF/s  "
+                f"{n / args.steps:5.1f} launches")
+        log(f"  (sum of launch times {total_ms / args.steps:.3f} ms of {t_mixed * 1e3:.3f} ms wall)")
+
+    out = {
+        "metric": "HT sum-truncations/s at d=64,n=1e4,k=64; mixed vs FP64 at rel err <=1e-6",
+        "value": 1.0 / t_mixed,
+        "unit": "sum-truncations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded; float32 N(0,1) leaf frames, transfer tensors with singular values 0.9^i)",
+        "config": {"workload": "HT sum truncation d=64 n=10000 k=64+64 -> rel tol 1e-6 (mixed precision)",
+                   "d": 64, "n": 10000, "k": 64, "sum_rank": 128, "eps": cfg["eps"], "rank_rule": "tolerance",
+                   "parallelism": "single GPU"},
+        "fp64_value": 1.0 / t_fp64,
+        "fp64_ms_per_step": t_fp64 * 1e3,
+        "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+        "fixed_r64_value": 1.0 / t_fixed,
+        "ranks_chosen": [min(ranks), max(ranks)],
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline (one sum-truncation)")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -58,11 +58,12 @@ typedef enum {
 typedef enum { HT_F64 = 0, HT_F32 = 1 } ht_dtype;
 
 /* HT_PREC_FP64: every product in float64 on the FP64 matrix cores.
- * HT_PREC_MIXED: forward products (R-factor contractions, projections, the
- *   first CholeskyQR2 sweep of the leaf frames) in float32 on the FP32 matrix
- *   cores with float32 accumulation; Cholesky factors, inverses, the second
- *   CholeskyQR2 sweep, the formation of orthogonal factors, the Gramian pass
- *   and the eigensolves in float64. */
+ * HT_PREC_MIXED: the first CholeskyQR2 sweep (the Gram matrices of the leaf
+ *   frames and of M_{2,3} of every transfer tensor) on the FP32 matrix cores
+ *   with float32 accumulation; the float64 second sweep removes its error.
+ *   Cholesky factors, inverses, the R-factor contractions, the orthogonal
+ *   factors, the Gramian pass, the eigensolves and the projections are float64
+ *   (float32 there costs ~1e-6 relative error at d = 64). */
 typedef enum { HT_PREC_FP64 = 0, HT_PREC_MIXED = 1 } ht_precision;
 
 /* Truncation rank rule (Section 3.3 "for prescribed ranks or for prescribed
@@ -78,6 +79,8 @@ typedef enum { HT_RANK_FIXED = 0, HT_RANK_TOL = 1 } ht_rank_mode;
 #define HT_FLAG_RANK_DEFICIENT 1u   /* a Cholesky pivot vanished: that direction was dropped */
 #define HT_FLAG_NONFINITE      2u   /* a NaN or Inf was met */
 #define HT_FLAG_CAPPED         4u   /* max_rank stopped a node before eps was met */
+/* bits 8-15 of the flags word: the largest number of QL iterations per
+ * eigenvalue (rounded down) any node's eigensolve needed (diagnostic) */
 
 typedef struct ht_context ht_context;
 
@@ -193,6 +196,26 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
 ht_status ht_entries_workspace(ht_context* ctx, const ht_desc* X, int64_t m, size_t* bytes);
 ht_status ht_entries(ht_context* ctx, const ht_desc* X, int64_t m, const int32_t* idx, double* out,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- profiling
+ * When enabled, every launch the library makes is bracketed by two HIP events
+ * on the caller's stream.  ht_profile_read() waits for the recorded events,
+ * folds them into per-(step, kernel) totals and returns up to max_entries of
+ * them (*n_out = number available).  flops and bytes are the algorithmic
+ * floating-point operations and the compulsory bytes (each operand read once,
+ * each result written once) of the launches, fixed when the launch is planned.
+ * ht_profile_reset() clears the totals.  Errors: HT_EINVAL, HT_EDEVICE. */
+typedef struct {
+  char label[48];             /* step of the method, e.g. "gramian_son1" */
+  char kernel[48];            /* kernel launched, e.g. "gemm_kernel<float,double,double>" */
+  int64_t launches;
+  double ms;                  /* summed event time of those launches */
+  double flops;
+  double bytes;
+} ht_profile_entry;
+ht_status ht_profile_enable(ht_context* ctx, int32_t on);
+ht_status ht_profile_read(ht_context* ctx, int32_t max_entries, ht_profile_entry* out, int32_t* n_out);
+ht_status ht_profile_reset(ht_context* ctx);
 
 #ifdef __cplusplus
 }

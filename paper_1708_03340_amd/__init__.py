@@ -27,6 +27,7 @@ EXPORTS = [
     "ht_create_context", "ht_destroy_context", "ht_status_string", "ht_last_error", "ht_version",
     "ht_tree", "ht_add", "ht_orthogonalize_workspace", "ht_orthogonalize", "ht_gramians_workspace",
     "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_entries_workspace", "ht_entries",
+    "ht_profile_enable", "ht_profile_read", "ht_profile_reset",
 ]
 
 
@@ -52,6 +53,17 @@ class HtTruncOpts(ctypes.Structure):
         ("eps_relative", ctypes.c_int32),
         ("max_rank", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+    ]
+
+
+class HtProfileEntry(ctypes.Structure):
+    _fields_ = [
+        ("label", ctypes.c_char * 48),
+        ("kernel", ctypes.c_char * 48),
+        ("launches", ctypes.c_int64),
+        ("ms", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes", ctypes.c_double),
     ]
 
 
@@ -89,6 +101,9 @@ def lib(path: Optional[str] = None):
                               VP, VP, ctypes.c_size_t, VP]
     L.ht_entries_workspace.argtypes = [VP, P(HtDesc), I64, P(ctypes.c_size_t)]
     L.ht_entries.argtypes = [VP, P(HtDesc), I64, VP, VP, VP, ctypes.c_size_t, VP]
+    L.ht_profile_enable.argtypes = [VP, I32]
+    L.ht_profile_read.argtypes = [VP, I32, P(HtProfileEntry), P(I32)]
+    L.ht_profile_reset.argtypes = [VP]
     for name in EXPORTS:
         if name not in ("ht_status_string", "ht_last_error", "ht_version", "ht_destroy_context"):
             getattr(L, name).restype = ctypes.c_int
@@ -443,3 +458,25 @@ def ht_entries(X: DeviceHT, idx, ctx=None, stream=None):
     _check(lib().ht_entries(ctx.h, ctypes.byref(d), m, _ptr(idx), _ptr(out), _ptr(ws), ws.numel(),
                             _stream_ptr(stream)))
     return out
+
+
+# ---------------------------------------------------------------- profiling
+def profile_enable(on=True, ctx=None):
+    ctx = ctx or ht_create_context()
+    _check(lib().ht_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_reset(ctx=None):
+    ctx = ctx or ht_create_context()
+    _check(lib().ht_profile_reset(ctx.h))
+
+
+def profile_read(ctx=None):
+    """Per (step, kernel) totals of the launches timed with HIP events."""
+    ctx = ctx or ht_create_context()
+    n = ctypes.c_int32(0)
+    _check(lib().ht_profile_read(ctx.h, 0, None, ctypes.byref(n)))
+    arr = (HtProfileEntry * max(1, n.value))()
+    _check(lib().ht_profile_read(ctx.h, n.value, arr, ctypes.byref(n)))
+    return [dict(label=e.label.decode(), kernel=e.kernel.decode(), launches=int(e.launches), ms=float(e.ms),
+                 flops=float(e.flops), bytes=float(e.bytes)) for e in arr[:n.value]]

@@ -70,7 +70,7 @@ namespace {
 
 enum OpKind : int {
   OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
-  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_FINISHR
 };
 
 struct Op {
@@ -86,7 +86,21 @@ struct Op {
   int i0 = 0, i1 = 0, i2 = 0, i3 = 0, i4 = 0, i5 = 0;
   double f0 = 0.0;
   int64_t c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // OP_COPY sizes and strides
+  const char* label = "";    // step of the method this launch belongs to
+  double flops = 0.0;        // algorithmic flops of the launch
+  double bytes_alg = 0.0;    // compulsory bytes moved by the launch
 };
+
+// Label given to the launches added next (one per step of the method).
+static thread_local const char* g_label = "";
+struct Label {
+  const char* prev;
+  explicit Label(const char* l) : prev(g_label) { g_label = l; }
+  ~Label() { g_label = prev; }
+};
+
+// Name of the kernel an op launches (as rocprof lists it, abbreviated).
+static std::string kernel_name(const Op& op);
 
 struct Plan {
   std::vector<Op> ops;
@@ -109,12 +123,8 @@ size_t put(Plan& P, const std::vector<T>& v) {
 
 int esize(int t) { return t == F32 ? 4 : 8; }
 
-// Jacobi scratch: A and V (K^2 each) and one sweep of rotations, (Ke-1) x Ke/2
-// pairs of (c, s) with Ke = K rounded up to even.
-size_t eig_scratch_doubles(int K) {
-  const size_t Ke = (size_t)K + (K & 1);
-  return 2 * (size_t)K * K + (Ke - 1) * Ke;
-}
+// Eigensolver scratch: the Householder reflectors (K x K) and their tau (K).
+size_t eig_scratch_doubles(int K) { return (size_t)K * K + (size_t)K + 64; }
 
 GemmDesc blank_desc() {
   GemmDesc d;
@@ -127,13 +137,24 @@ GemmDesc blank_desc() {
 
 // Adds one GEMM launch over `descs` (all sharing types, math, mode, layouts).
 void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode,
-              bool akc, bool bkc, int target_blocks = 4096) {
+              bool akc, bool bkc, bool acc64 = false, int target_blocks = 4096) {
   if (descs.empty()) return;
   Op op;
   op.kind = OP_GEMM;
+  // large float64 problems use 128 x 128 tiles
+  // (only when there are enough output tiles to fill the chip without
+  // splitting the reduction; split-K problems keep 64 x 64 tiles)
+  bool big = math == MATH_F64 && mode == GEMM_STORE;
+  long long tiles128 = 0;
+  for (const auto& d : descs) {
+    if (d.kr || d.M < 96 || d.N < 96) big = false;
+    tiles128 += (long long)((d.M + 127) / 128) * ((d.N + 127) / 128) * d.nbatch;
+  }
+  if (tiles128 < 512) big = false;
+  const int tile = big ? 128 : 64;
   int maxtiles = 0, maxbatch = 1, maxkt = 1;
   for (const auto& d : descs) {
-    const int tiles = ((d.M + 63) / 64) * ((d.N + 63) / 64);
+    const int tiles = ((d.M + tile - 1) / tile) * ((d.N + tile - 1) / tile);
     maxtiles = std::max(maxtiles, tiles);
     maxbatch = std::max(maxbatch, d.nbatch);
     int kt = 0;
@@ -149,10 +170,22 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
   }
   op.g.tA = tA; op.g.tB = tB; op.g.tC = tC; op.g.math = math; op.g.mode = mode;
   op.g.a_kcontig = akc; op.g.b_kcontig = bkc;
+  op.g.acc64 = acc64 && math == MATH_F32;
+  op.g.big = big;
   op.g.splitk = split;
   op.g.ndesc = (int)descs.size();
   op.g.maxbatch = maxbatch;
   op.g.maxtiles = maxtiles;
+  op.label = g_label;
+  for (const auto& d : descs) {
+    double kt = 0.0;
+    if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
+    else kt = (double)d.KB * d.K;
+    const double nb = d.nbatch;
+    op.flops += 2.0 * nb * d.M * d.N * kt;
+    op.bytes_alg += nb * ((double)d.M * kt * (tA == F32 ? 4 : 8) + kt * d.N * (tB == F32 ? 4 : 8) +
+                          (double)d.M * d.N * (tC == F32 ? 4 : 8));
+  }
   op.toff = put(P, descs);
   op.count = (int)descs.size();
   P.ops.push_back(op);
@@ -162,6 +195,8 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
   if (a.empty()) return;
   Op op;
   op.kind = kind;
+  op.label = g_label;
+  for (const auto& x : a) op.bytes_alg += 2.0 * 8.0 * x.K * x.K;
   op.toff = put(P, a);
   op.count = (int)a.size();
   P.ops.push_back(op);
@@ -169,13 +204,14 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
 
 void add_fill(Plan& P, void* ptr, size_t bytes) {
   if (!bytes) return;
-  Op op; op.kind = OP_FILL; op.p0 = ptr; op.bytes = bytes;
+  Op op; op.kind = OP_FILL; op.p0 = ptr; op.bytes = bytes; op.label = g_label;
   P.ops.push_back(op);
 }
 
 void add_copy3(Plan& P, const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
                int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2, double alpha) {
   Op op; op.kind = OP_COPY; op.p0 = const_cast<void*>(src); op.p1 = dst; op.i0 = tsrc; op.i1 = tdst;
+  op.label = g_label;
   const int64_t v[9] = {n0, n1, n2, s0, s1, s2, d0, d1, d2};
   for (int i = 0; i < 9; ++i) op.c[i] = v[i];
   op.f0 = alpha;
@@ -198,11 +234,29 @@ void build_key(Plan& P) {
 
 }  // namespace
 
+struct ProfPending { hipEvent_t a, b; const char* label; std::string kernel; double flops, bytes; };
+struct ProfAgg { std::string label, kernel; long long n = 0; double ms = 0, flops = 0, bytes = 0; };
+
 struct ht_context {
   int device = 0;
   std::mutex mu;
   std::list<Plan> cache;   // most recent first
+  bool prof = false;
+  std::vector<hipEvent_t> free_events;
+  std::vector<ProfPending> pending;
+  std::vector<ProfAgg> agg;
 };
+
+static hipEvent_t take_event(ht_context* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
 
 namespace {
 
@@ -238,6 +292,12 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
   char* tb = reinterpret_cast<char*>(dtable);
   for (auto& op : P.ops) {
     hipError_t e = hipSuccess;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->prof) {
+      ev0 = take_event(ctx);
+      ev1 = take_event(ctx);
+      if (ev0) (void)hipEventRecord(ev0, stream);
+    }
     switch (op.kind) {
       case OP_GEMM: {
         GemmLaunch g = op.g;
@@ -249,6 +309,10 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
       case OP_CHOL2:
         e = launch_chol(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
                         op.kind == OP_CHOL1 ? 1 : 2, stream, reinterpret_cast<GlobalState*>(op.p0));
+        break;
+      case OP_FINISHR:
+        e = launch_finish_r(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, stream,
+                            reinterpret_cast<GlobalState*>(op.p0));
         break;
       case OP_EIG:
         e = launch_eig(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, nullptr, stream,
@@ -299,8 +363,37 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
         break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (ctx->prof && ev0 && ev1) {
+      (void)hipEventRecord(ev1, stream);
+      const std::string kn = kernel_name(op);
+      ctx->pending.push_back({ev0, ev1, (op.label && *op.label) ? op.label : "other", kn, op.flops, op.bytes_alg});
+    }
   }
   return HT_OK;
+}
+
+std::string kernel_name(const Op& op) {
+  auto tn = [](int t) { return t == F32 ? "float" : "double"; };
+  switch (op.kind) {
+    case OP_GEMM:
+      return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +
+             (op.g.math == MATH_F32 ? "float" : "double") + ">";
+    case OP_CHOL1: case OP_CHOL2: return "chol_kernel";
+    case OP_FINISHR: return "finish_r_kernel";
+    case OP_EIG: return "eig_kernel";
+    case OP_RANK: return "rank_kernel";
+    case OP_PROJPREP: return "proj_prep_kernel";
+    case OP_SIGMA: return "sigma_kernel";
+    case OP_ROOTNORM: return "root_norm_kernel";
+    case OP_FILL: return "fill_kernel";
+    case OP_SETSTATE: return "set_state_kernel";
+    case OP_WRITESCALE: return "write_scale_kernel";
+    case OP_COPY: return "copy3_kernel";
+    case OP_EGATHER: return "gather_kernel";
+    case OP_ENORM: return "normalize_kernel";
+    case OP_EFINISH: return "finish_kernel";
+  }
+  return "?";
 }
 
 // ------------------------------------------------------------------ validation
@@ -355,7 +448,8 @@ struct Arena {
 // Per-node buffers of the truncation / orthogonalisation.
 struct NodeBufs {
   int K = 0, rcap = 0;
-  double *G = nullptr, *G2 = nullptr, *Bh = nullptr, *R1 = nullptr, *Ri1 = nullptr, *R = nullptr,
+  double *G = nullptr, *G2 = nullptr, *Bh = nullptr, *R1 = nullptr, *Ri1 = nullptr, *R2 = nullptr,
+         *R2i = nullptr, *R = nullptr,
          *Ri = nullptr, *Q = nullptr, *lam = nullptr, *Qm = nullptr, *scratch = nullptr;
   void *Rf = nullptr, *QmT = nullptr, *Pm = nullptr;
   int32_t* rank = nullptr;
@@ -429,8 +523,15 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
                const std::vector<int>& rcap, bool need_proj_bufs, const ht_desc* out,
                const ht_desc* inplace) {
   const int nn = tr.nn, d = tr.d;
-  const int T = prec == HT_PREC_MIXED ? F32 : F64;          // forward-product type
-  const int fmath = prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64;
+  // Precision policy.  The first CholeskyQR2 sweeps (leaf frames and M_{2,3}
+  // of every transfer tensor) run on the FP32 matrix cores in the mixed path:
+  // the float64 second sweep removes their error.  Every other product, and
+  // all storage, is float64: at d = 64 each float32 stage of the forward
+  // contractions or projections adds a few 1e-7 to the relative error of the
+  // truncated tensor, and together they exceed 1e-6.
+  const int T = F64;                                          // storage / forward-product type
+  const int fmath = MATH_F64;                                 // forward products
+  const int smath = prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64;  // first sweeps
   const int tsz = esize(T);
   const ht_desc& X0 = *S.X[0];
   O.nb.assign(nn, NodeBufs());
@@ -457,6 +558,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     b.rcap = rcap.empty() ? b.K : rcap[t];
     b.R1 = (double*)A.take(kk * 8);
     b.Ri1 = (double*)A.take(kk * 8);
+    b.R2 = (double*)A.take(kk * 8);
+    b.R2i = (double*)A.take(kk * 8);
     b.R = (double*)A.take(kk * 8);
     b.Ri = (double*)A.take(kk * 8);
     b.Rf = A.take(kk * tsz);
@@ -500,13 +603,15 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   }
 
   // ---- launches
+  g_label = "setup";
   {
-    Op op; op.kind = OP_SETSTATE; op.p0 = O.st; op.scale0 = S.scale0;
+    Op op; op.kind = OP_SETSTATE; op.p0 = O.st; op.scale0 = S.scale0; op.label = g_label;
     P.ops.push_back(op);
   }
   add_fill(P, zptr, zbytes);
 
   const int fdt = X0.frame_dtype, tdt = X0.transfer_dtype;
+  g_label = "leaf_gram_sweep1";
   // leaves: sweep 1 Gram G = W^T W (blocks of summand pairs)
   {
     std::vector<GemmDesc> ds;
@@ -523,8 +628,32 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
           ds.push_back(g);
         }
     }
-    add_gemm(P, ds, fdt, fdt, F64, prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64, GEMM_ATOMIC, true, true);
+    add_gemm(P, ds, fdt, fdt, F64, smath, GEMM_ATOMIC, true, true);
   }
+  // second CholeskyQR2 step: R = R2 R1 and R^{-1} = R1^{-1} R2^{-1} (FP64
+  // GEMMs), then R is normalised by a power of two
+  auto add_combine = [&](const std::vector<int>& nodes, const std::vector<SmallArgs>& a) {
+    std::vector<GemmDesc> dr, di;
+    for (int t : nodes) {
+      const NodeBufs& b = O.nb[t];
+      GemmDesc g = blank_desc();
+      g.A = b.R2; g.sAm = b.K; g.sAk = 1;
+      g.B = b.R1; g.sBk = b.K; g.sBn = 1;
+      g.C = b.R; g.sCm = b.K; g.sCn = 1;
+      g.M = g.N = g.K = b.K;
+      dr.push_back(g);
+      GemmDesc h = blank_desc();
+      h.A = b.Ri1; h.sAm = b.K; h.sAk = 1;
+      h.B = b.R2i; h.sBk = b.K; h.sBn = 1;
+      h.C = b.Ri; h.sCm = b.K; h.sCn = 1;
+      h.M = h.N = h.K = b.K;
+      di.push_back(h);
+    }
+    add_gemm(P, dr, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    add_gemm(P, di, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    add_small(P, OP_FINISHR, a);
+    P.ops.back().p0 = O.st;
+  };
   auto small_args = [&](const std::vector<int>& nodes, double tol) {
     std::vector<SmallArgs> v;
     for (int t : nodes) {
@@ -532,7 +661,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       SmallArgs a;
       std::memset(&a, 0, sizeof(a));
       a.K = b.K; a.node = t; a.rcap = b.rcap;
-      a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1; a.R = b.R; a.Ri = b.Ri; a.Rf = b.Rf;
+      a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1; a.R2 = b.R2; a.R2i = b.R2i;
+      a.R = b.R; a.Ri = b.Ri; a.Rf = b.Rf;
       a.rf_type = T; a.tol_rel = tol;
       a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rank_dev = b.rank; a.scratch = b.scratch;
       a.Bh = b.Bh;
@@ -544,6 +674,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   for (int mu = 0; mu < d; ++mu) leaves.push_back(tr.leaf_node[mu]);
   {
     Op op;
+    g_label = "leaf_chol1";
     auto a = small_args(leaves, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
     add_small(P, OP_CHOL1, a);
     P.ops.back().p0 = O.st;
@@ -567,6 +698,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       g.M = (int)X0.n[mu]; g.N = S.K[t]; g.K = 0;
       ds.push_back(g);
     }
+    g_label = "leaf_sweep2_form";
     add_gemm(P, ds, fdt, F64, F64, MATH_F64, GEMM_STORE, false, false);
     ds.clear();
     for (int mu = 0; mu < d; ++mu) {
@@ -578,12 +710,15 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       g.M = S.K[t]; g.N = S.K[t]; g.K = (int)X0.n[mu];
       ds.push_back(g);
     }
+    g_label = "leaf_sweep2_gram";
     add_gemm(P, ds, F64, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
   }
   {
+    g_label = "leaf_chol2";
     auto a = small_args(leaves, 1e-13);
     add_small(P, OP_CHOL2, a);
     P.ops.back().p0 = O.st;
+    add_combine(leaves, a);
   }
   // inner nodes by height
   const int H = tr.height[0];
@@ -618,8 +753,11 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
         toff += (size_t)kt * k1 * K2;
       }
     }
-    add_gemm(P, d3, tdt, T, T, fmath, GEMM_STORE, true, true);
-    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false);
+    g_label = "inner_mode3_R";
+    add_gemm(P, d3, tdt, T, T, fmath, GEMM_STORE, true, true, true);
+    g_label = "inner_mode2_R";
+    g_label = "proj_inner_mode2";
+    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
     // sweep 1: G = M1(Bp) M1(Bp)^T in float64
     std::vector<GemmDesc> dg;
     for (int t : nodes) {
@@ -632,9 +770,11 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       g.M = S.K[t]; g.N = S.K[t]; g.K = (int)w;
       dg.push_back(g);
     }
-    add_gemm(P, dg, T, T, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    g_label = "inner_gram_sweep1";
+    add_gemm(P, dg, T, T, F64, smath, GEMM_ATOMIC, true, true);
     {
-      auto a = small_args(nodes, 1e-12);
+      g_label = "inner_chol1";
+      auto a = small_args(nodes, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
       add_small(P, OP_CHOL1, a);
       P.ops.back().p0 = O.st;
     }
@@ -663,15 +803,21 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       q.M = S.K[t]; q.N = (int)w; q.K = S.K[t];
       dq.push_back(q);
     }
+    g_label = "inner_sweep2_form";
     add_gemm(P, dy, F64, T, F64, MATH_F64, GEMM_STORE, false, false);
+    g_label = "inner_sweep2_gram";
     add_gemm(P, dg2, F64, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
     {
+      g_label = "inner_chol2";
       auto a = small_args(nodes, 1e-13);
       add_small(P, OP_CHOL2, a);
       P.ops.back().p0 = O.st;
+      add_combine(nodes, a);
     }
+    g_label = "inner_orth_factor";
     add_gemm(P, dq, F64, T, inplace ? inplace->transfer_dtype : T, MATH_F64, GEMM_STORE, false, false);
   }
+  g_label = "root_orth";
   // root: HD = blockdiag(alpha_c B_D^(c)); BDo = R_t1 HD R_t2^T
   const int t1 = tr.son1[0], t2 = tr.son2[0];
   for (int c = 0; c < S.n_in; ++c) {
@@ -705,8 +851,10 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
                    const double* BDo, GlobalState* st, const std::vector<const void*>& Qo, int tq) {
   const int t1 = tr.son1[0], t2 = tr.son2[0];
   const int K1r = K[t1], K2r = K[t2];
+  g_label = "gramian_root";
   {
     Op op; op.kind = OP_ROOTNORM; op.p0 = st; op.p1 = const_cast<double*>(BDo); op.i0 = K1r; op.i1 = K2r;
+    op.label = g_label;
     P.ops.push_back(op);
   }
   {
@@ -755,8 +903,11 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
       q.M = K2; q.N = K2; q.K = Kt * K1;
       ds2.push_back(q);
     }
+    g_label = "gramian_mode1";
     add_gemm(P, dc, F64, tq, F64, MATH_F64, GEMM_STORE, true, false);
+    g_label = "gramian_son1";
     add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    g_label = "gramian_son2";
     add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false);
   }
 }
@@ -797,6 +948,8 @@ void ht_destroy_context(ht_context* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
   for (auto& p : ctx->cache) (void)hipFree(p.dtable);
+  for (auto& p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto& e : ctx->free_events) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -859,8 +1012,8 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     if (!out_scale) return fail(HT_EINVAL, "out_log2_scale is NULL");
   }
   const int prec = opts->precision;
-  const int T = prec == HT_PREC_MIXED ? F32 : F64;
-  const int fmath = prec == HT_PREC_MIXED ? MATH_F32 : MATH_F64;
+  const int T = F64;            // storage and forward products: see plan_orth
+  const int fmath = MATH_F64;
   const int tsz = esize(T);
   Arena A(ws);
   OrthOut O;
@@ -883,14 +1036,17 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     a.sigma_out = out_sigma ? out_sigma + (size_t)t * KMAX : nullptr;
     sa.push_back(a);
   }
+  g_label = "eig";
   add_small(P, OP_EIG, sa);
   P.ops.back().p0 = O.st;
+  g_label = "rank_select";
   add_small(P, OP_RANK, sa);
   {
     Op& op = P.ops.back();
     op.p0 = O.st; op.i0 = d; op.i1 = opts->mode; op.f0 = opts->eps; op.i2 = opts->eps_relative ? 1 : 0;
     op.i3 = opts->max_rank; op.i4 = tr.son1[0]; op.i5 = tr.son2[0];
   }
+  g_label = "proj_prep";
   add_small(P, OP_PROJPREP, sa);
   P.ops.back().p0 = O.st;
   // projections (eq. (nodewisetruncation), eq. (transfertransformationtrunc), root rule)
@@ -944,11 +1100,18 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
       q.M = b.rcap * O.nb[s1].rcap; q.N = O.nb[s2].rcap; q.K = K2;
       d3.push_back(q);
     }
+    g_label = "proj_leaf_factor";
     add_gemm(P, dp, F64, F64, T, MATH_F64, GEMM_STORE, true, false);
-    add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false);
-    add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false);
-    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false);
-    add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true);
+    g_label = "proj_leaf";
+    add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false, true);
+    g_label = "proj_inner_mode1";
+    add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false, true);
+    g_label = "inner_mode2_R";
+    g_label = "proj_inner_mode2";
+    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
+    g_label = "proj_inner_mode3";
+    add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true, true);
+    g_label = "proj_root";
     // root: Qm_t1^T BDo Qm_t2
     const int t1 = tr.son1[0], t2 = tr.son2[0];
     const int K1r = S.K[t1], K2r = S.K[t2];
@@ -1355,6 +1518,59 @@ ht_status ht_add(ht_context* ctx, double alpha, const ht_desc* A, double beta, c
 
 }  // extern "C"
 
+// ================================================================== profiling
+extern "C" {
+
+ht_status ht_profile_enable(ht_context* ctx, int32_t on) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  ctx->prof = on != 0;
+  return HT_OK;
+}
+
+ht_status ht_profile_read(ht_context* ctx, int32_t max_entries, ht_profile_entry* out, int32_t* n_out) {
+  if (!ctx || !n_out) return fail(HT_EINVAL, "NULL argument");
+  for (auto& p : ctx->pending) {
+    HT_HIP(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HT_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    ProfAgg* a = nullptr;
+    for (auto& x : ctx->agg)
+      if (x.label == p.label && x.kernel == p.kernel) { a = &x; break; }
+    if (!a) {
+      ctx->agg.push_back(ProfAgg());
+      a = &ctx->agg.back();
+      a->label = p.label;
+      a->kernel = p.kernel;
+    }
+    a->n += 1; a->ms += ms; a->flops += p.flops; a->bytes += p.bytes;
+    ctx->free_events.push_back(p.a);
+    ctx->free_events.push_back(p.b);
+  }
+  ctx->pending.clear();
+  const int n = (int)ctx->agg.size();
+  *n_out = n;
+  for (int i = 0; i < n && i < max_entries && out; ++i) {
+    std::memset(&out[i], 0, sizeof(ht_profile_entry));
+    std::strncpy(out[i].label, ctx->agg[i].label.c_str(), sizeof(out[i].label) - 1);
+    std::strncpy(out[i].kernel, ctx->agg[i].kernel.c_str(), sizeof(out[i].kernel) - 1);
+    out[i].launches = ctx->agg[i].n;
+    out[i].ms = ctx->agg[i].ms;
+    out[i].flops = ctx->agg[i].flops;
+    out[i].bytes = ctx->agg[i].bytes;
+  }
+  return HT_OK;
+}
+
+ht_status ht_profile_reset(ht_context* ctx) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  int32_t n = 0;
+  ht_status s = ht_profile_read(ctx, 0, nullptr, &n);
+  ctx->agg.clear();
+  return s;
+}
+
+}  // extern "C"
+
 // ================================================================== bounds validation (host only)
 // Builds a plan against fake, disjoint address ranges sized from the shapes
 // (user buffers and every workspace allocation) and checks that every byte a
@@ -1436,7 +1652,8 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         const int nseg = g.nseg > 0 ? g.nseg : g.KB;
         const std::string w = tag + " desc " + std::to_string(i);
         if (g.nbatch > op.g.maxbatch) return fail(HT_EINVAL, "validator: batch " + w);
-        if (((g.M + 63) / 64) * ((g.N + 63) / 64) > op.g.maxtiles) return fail(HT_EINVAL, "validator: tiles " + w);
+        const int tl = op.g.big ? 128 : 64;
+        if (((g.M + tl - 1) / tl) * ((g.N + tl - 1) / tl) > op.g.maxtiles) return fail(HT_EINVAL, "validator: tiles " + w);
         for (int sg = 0; sg < nseg; ++sg) {
           const int ks = g.nseg > 0 ? g.segK[sg] : g.K;
           if (ks <= 0) continue;
@@ -1461,6 +1678,14 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (s) return s;
         if (g.alpha_dev) { s = check_range(g.alpha_dev, 0, 0, 8, w + " alpha"); if (s) return s; }
       }
+    } else if (op.kind == OP_FINISHR) {
+      const SmallArgs* as = reinterpret_cast<const SmallArgs*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const int64_t kk = (int64_t)as[i].K * as[i].K;
+        if ((s = check_range(as[i].R, 0, kk - 1, 8, tag + " R")) ||
+            (s = check_range(as[i].Rf, 0, kk - 1, esize(as[i].rf_type), tag + " Rf")))
+          return s;
+      }
     } else if (op.kind == OP_CHOL1 || op.kind == OP_CHOL2 || op.kind == OP_EIG || op.kind == OP_RANK ||
                op.kind == OP_PROJPREP || op.kind == OP_SIGMA) {
       const SmallArgs* as = reinterpret_cast<const SmallArgs*>(at(op.toff));
@@ -1476,12 +1701,11 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
           if ((s = chk(a.G, kk, 8, "G")) || (s = chk(a.G2, kk, 8, "G2")) || (s = chk(a.R1, kk, 8, "R1")) ||
               (s = chk(a.Ri1, kk, 8, "Ri1")))
             return s;
-          if (op.kind == OP_CHOL2 && ((s = chk(a.R, kk, 8, "R")) || (s = chk(a.Ri, kk, 8, "Ri")) ||
-                                      (s = chk(a.Rf, kk, esize(a.rf_type), "Rf"))))
+          if (op.kind == OP_CHOL2 && ((s = chk(a.R2, kk, 8, "R2")) || (s = chk(a.R2i, kk, 8, "R2i"))))
             return s;
         } else if (op.kind == OP_EIG) {
           if ((s = chk(a.Bh, kk, 8, "Bh")) || (s = chk(a.Q, kk, 8, "Q")) || (s = chk(a.lam, a.K, 8, "lam")) ||
-              (s = chk(a.scratch, 2 * kk + (int64_t)(a.K + (a.K & 1) - 1) * (a.K + (a.K & 1)), 8, "scratch")))
+              (s = chk(a.scratch, kk + a.K, 8, "scratch")))
             return s;
         } else if (op.kind == OP_RANK) {
           if ((s = chk(a.lam, a.K, 8, "lam")) || (s = chk(a.rank_dev, 1, 4, "rank"))) return s;

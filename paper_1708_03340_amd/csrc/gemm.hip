@@ -35,7 +35,7 @@ struct Cursor {
   int k0;    // offset inside the segment
 };
 
-template <typename TA, typename TB, typename TM>
+template <typename TA, typename TB, typename TM, bool ACC64>
 __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ descs, int maxbatch,
                                                   int splitk, int tC, int mode, int aK, int bK) {
   __shared__ TM As[BK][BM + 4];
@@ -129,6 +129,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = V{0, 0, 0, 0};
+  // ACC64: the float32 MFMA accumulator is emptied into float64 registers
+  // after every k-slab, so rounding grows with the slab (16), not with K
+  doublex4 acc64[2][2];
+  if (ACC64) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc64[i][j] = doublex4{0, 0, 0, 0};
+  }
 
   if (t0 < t1) {
     load(cur);
@@ -148,6 +157,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
         acc[0][1] = mfma16(a0, b1, acc[0][1]);
         acc[1][0] = mfma16(a1, b0, acc[1][0]);
         acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      }
+      if (ACC64) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              acc64[i][j][v] += (double)acc[i][j][v];
+              acc[i][j][v] = (TM)0;
+            }
       }
       __syncthreads();
       if (more) {
@@ -174,7 +194,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
         const int row = tm * BM + wm * 32 + i * 16 + rin;
         const int col = tn * BN + wn * 32 + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          const double val = alpha * (double)acc[i][j][v];
+          const double val = alpha * (ACC64 ? acc64[i][j][v] : (double)acc[i][j][v]);
           const int64_t off = coff_b + (int64_t)row * D.sCm + (int64_t)col * D.sCn;
           if (tC == F64) {
             double* p = reinterpret_cast<double*>(Cb) + off;
@@ -188,11 +208,175 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
   (void)esz;
 }
 
-template <typename TA, typename TB, typename TM>
+template <typename TA, typename TB, typename TM, bool ACC64 = false>
 hipError_t go(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.maxtiles, g.splitk, g.ndesc * g.maxbatch);
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, TM>), grid, dim3(NT), 0, s, g.descs, g.maxbatch, g.splitk,
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TM, ACC64>), grid, dim3(NT), 0, s, g.descs, g.maxbatch, g.splitk,
                      g.tC, g.mode, g.a_kcontig ? 1 : 0, g.b_kcontig ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ 128 x 128 float64 tiles
+// For the large float64 contractions: 128 x 128 output tile per workgroup,
+// four waves of 64 x 64 (4 x 4 MFMA 16x16x4 blocks: 16 MFMAs per 8 LDS
+// fragment reads), k-slabs of 16 double-buffered in LDS (one barrier per
+// slab) with the next slab prefetched into registers while the current one
+// is multiplied.  Operands of any type are widened to float64 on the way
+// into LDS.
+constexpr int BT = 128, PADT = 4;
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(NT, 2) void gemm128_kernel(const GemmDesc* __restrict__ descs, int maxbatch,
+                                                       int splitk, int tC, int mode, int aK, int bK) {
+  __shared__ double As[2][BK][BT + PADT];
+  __shared__ double Bs[2][BK][BT + PADT];
+
+  const GemmDesc& D = descs[blockIdx.z / maxbatch];
+  const int b = blockIdx.z % maxbatch;
+  if (b >= D.nbatch) return;
+  const int M = D.M, N = D.N;
+  const int tilesN = (N + BT - 1) / BT;
+  const int tilesM = (M + BT - 1) / BT;
+  if ((int)blockIdx.x >= tilesM * tilesN) return;
+  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+
+  const int nseg = D.nseg > 0 ? D.nseg : D.KB;
+  auto segK = [&](int s) -> int { return D.nseg > 0 ? D.segK[s] : D.K; };
+  int total = 0;
+  for (int s = 0; s < nseg; ++s) total += (segK(s) + BK - 1) / BK;
+  const int per = (total + splitk - 1) / splitk;
+  const int t0 = blockIdx.y * per;
+  const int t1 = min(total, t0 + per);
+  if (t0 >= t1 && !(mode == GEMM_STORE && blockIdx.y == 0)) return;
+
+  const TA* Ab = reinterpret_cast<const TA*>(D.A);
+  const TB* Bb = reinterpret_cast<const TB*>(D.B);
+  const int64_t aoff_b = (int64_t)b * D.sAb, boff_b = (int64_t)b * D.sBb;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // each thread moves 8 elements of A and 8 of B per slab
+  //   k-contiguous operand: row r = tid/2, k = (tid%2)*8 + i
+  //   row-contiguous operand: k = tid/16, row r = (tid%16)*8 + i
+  const int a_r0 = aK ? (tid >> 1) : (tid & 15) * 8;
+  const int a_k0 = aK ? (tid & 1) * 8 : (tid >> 4);
+  const int b_r0 = bK ? (tid >> 1) : (tid & 15) * 8;
+  const int b_k0 = bK ? (tid & 1) * 8 : (tid >> 4);
+
+  Cursor cur{0, 0};
+  {
+    int skip = t0;
+    while (cur.seg < nseg) {
+      int nt = (segK(cur.seg) + BK - 1) / BK;
+      if (skip < nt) { cur.k0 = skip * BK; break; }
+      skip -= nt;
+      cur.seg++;
+    }
+  }
+
+  double ra[8], rb[8];
+  auto load = [&](const Cursor& c) {
+    const int s = c.seg;
+    const int ks = segK(s);
+    const TA* Ap = (D.nseg > 0 ? reinterpret_cast<const TA*>(D.segA[s]) : Ab + (int64_t)s * D.sAkb) + aoff_b;
+    const TB* Bp = Bb + (D.nseg > 0 ? D.segBoff[s] : (int64_t)s * D.sBkb) + boff_b;
+    const int64_t sAk = D.nseg > 0 ? D.segAk[s] : D.sAk;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = aK ? a_r0 : a_r0 + i, k = aK ? a_k0 + i : a_k0;
+      const int gm = tm * BT + r, gk = c.k0 + k;
+      ra[i] = (gm < M && gk < ks) ? (double)Ap[(int64_t)gm * D.sAm + (int64_t)gk * sAk] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = bK ? b_r0 : b_r0 + i, k = bK ? b_k0 + i : b_k0;
+      const int gn = tn * BT + r, gk = c.k0 + k;
+      rb[i] = (gn < N && gk < ks) ? (double)Bp[(int64_t)gk * D.sBk + (int64_t)gn * D.sBn] : 0.0;
+    }
+  };
+  auto advance = [&](Cursor& c) {
+    c.k0 += BK;
+    if (c.k0 >= segK(c.seg)) { c.seg++; c.k0 = 0; }
+    while (c.seg < nseg && segK(c.seg) == 0) c.seg++;
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (aK) As[buf][a_k0 + i][a_r0] = ra[i]; else As[buf][a_k0][a_r0 + i] = ra[i];
+      if (bK) Bs[buf][b_k0 + i][b_r0] = rb[i]; else Bs[buf][b_k0][b_r0 + i] = rb[i];
+    }
+  };
+
+  doublex4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+
+  if (t0 < t1) {
+    load(cur);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int it = t0; it < t1; ++it) {
+      const bool more = it + 1 < t1;
+      if (more) { advance(cur); load(cur); }
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          fa[i] = As[buf][kr][wm * 64 + i * 16 + (lane & 15)];
+          fb[i] = Bs[buf][kr][wn * 64 + i * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(fa[i], fb[j], acc[i][j]);
+      }
+      if (more) {
+        stash(buf ^ 1);
+        buf ^= 1;
+      }
+      __syncthreads();
+    }
+  }
+
+  double alpha = D.alpha;
+  if (D.alpha_dev) alpha *= *D.alpha_dev;
+  char* Cb = reinterpret_cast<char*>(D.C);
+  const int64_t coff_b = (int64_t)b * D.sCb;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // FP64 16x16x4: register v of lane l holds row 4v + l/16, column l%16
+        const int row = tm * BT + wm * 64 + i * 16 + v * 4 + (lane >> 4);
+        const int col = tn * BT + wn * 64 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          const double val = alpha * acc[i][j][v];
+          const int64_t off = coff_b + (int64_t)row * D.sCm + (int64_t)col * D.sCn;
+          if (tC == F64) {
+            double* p = reinterpret_cast<double*>(Cb) + off;
+            if (mode == GEMM_ATOMIC) atomicAdd(p, val); else *p = val;
+          } else {
+            float* p = reinterpret_cast<float*>(Cb) + off;
+            if (mode == GEMM_ATOMIC) atomicAdd(p, (float)val); else *p = (float)val;
+          }
+        }
+      }
+}
+
+template <typename TA, typename TB>
+hipError_t go128(const GemmLaunch& g, hipStream_t s) {
+  dim3 grid(g.maxtiles, g.splitk, g.ndesc * g.maxbatch);
+  hipLaunchKernelGGL((gemm128_kernel<TA, TB>), grid, dim3(NT), 0, s, g.descs, g.maxbatch, g.splitk, g.tC,
+                     g.mode, g.a_kcontig ? 1 : 0, g.b_kcontig ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -201,6 +385,18 @@ hipError_t go(const GemmLaunch& g, hipStream_t s) {
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s) {
   if (g.ndesc <= 0 || g.maxtiles <= 0) return hipSuccess;
   const bool a32 = g.tA == F32, b32 = g.tB == F32;
+  if (g.big) {
+    if (a32 && b32) return go128<float, float>(g, s);
+    if (a32 && !b32) return go128<float, double>(g, s);
+    if (!a32 && b32) return go128<double, float>(g, s);
+    return go128<double, double>(g, s);
+  }
+  if (g.math == MATH_F32 && g.acc64) {
+    if (a32 && b32) return go<float, float, float, true>(g, s);
+    if (a32 && !b32) return go<float, double, float, true>(g, s);
+    if (!a32 && b32) return go<double, float, float, true>(g, s);
+    return go<double, double, float, true>(g, s);
+  }
   if (g.math == MATH_F32) {
     if (a32 && b32) return go<float, float, float>(g, s);
     if (a32 && !b32) return go<float, double, float>(g, s);

@@ -57,6 +57,8 @@ struct GemmLaunch {
   bool a_kcontig;          // sAk == 1 (else sAm == 1)
   bool b_kcontig;          // sBk == 1 (else sBn == 1)
   int splitk;              // blocks along the reduction (GEMM_ATOMIC if > 1)
+  bool acc64;              // MATH_F32 only: float64 accumulation across k-slabs
+  bool big;                // MATH_F64 only: 128 x 128 tiles
   int ndesc, maxbatch, maxtiles;
   const GemmDesc* descs;   // device pointer
 };
@@ -73,6 +75,8 @@ struct SmallArgs {
   double* G2;              // K x K second-sweep Gram
   double* R1;              // K x K first-sweep factor
   double* Ri1;             // K x K inverse of the first-sweep factor
+  double* R2;              // K x K second-sweep factor
+  double* R2i;             // K x K its inverse (unit diagonal on dropped rows)
   double* R;               // K x K upper factor (output, normalised by 2^-e)
   double* Ri;              // K x K inverse of the unnormalised factor
   double tol_rel;          // pivot tolerance relative to the largest diagonal entry
@@ -102,6 +106,7 @@ struct GlobalState {       // device-resident per-call scalars
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);   // bytes: multiple of 4
 hipError_t launch_set_state(GlobalState* st, long long scale0, hipStream_t s);
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);
+hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st);
 hipError_t launch_eig(const SmallArgs* args, int n, double* scratch, hipStream_t s, GlobalState* st);
 hipError_t launch_rank_select(const SmallArgs* args, int n, int d, int mode, double eps, int rel,
                               int max_rank, int t1, int t2, GlobalState* st, hipStream_t s);

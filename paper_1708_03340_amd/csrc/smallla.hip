@@ -53,266 +53,351 @@ __device__ __forceinline__ int exp2_of(double x) {
   return e;
 }
 
-// In-place Cholesky G = R^T R of the K x K matrix in L (upper triangle used).
+// In-place Cholesky G = R^T R of the K x K matrix in L (upper triangle used),
+// right-looking in the LDL^T form: rows stay unscaled during the elimination
+// (one barrier per step) and are divided by sqrt(pivot) at the end.
 // sweep 1: pivots <= tol are replaced by tol; sweep 2: such rows are dropped
-// (set to zero, dropped[j] = 1).  Returns true if anything was dropped/clamped.
-__device__ bool chol_lds(double* L, int K, double tol, int sweep, int* dropped) {
+// (set to zero, dropped[j] = 1).  Returns true if anything was dropped.
+__device__ bool chol_lds(double* L, int K, int ld, double tol, int sweep, int* dropped, double* piv) {
   const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
   __shared__ int any;
   if (tid == 0) any = 0;
   __syncthreads();
   for (int j = 0; j < K; ++j) {
-    double piv = L[j * K + j];
+    double pj = L[j * ld + j];
     bool drop = false;
-    if (!(piv > tol)) {
-      if (sweep == 1) piv = tol; else drop = true;
+    if (!(pj > tol)) {
+      if (sweep == 1) pj = tol; else drop = true;
     }
-    __syncthreads();
-    if (drop) {
-      for (int c = j + tid; c < K; c += NT) L[j * K + c] = 0.0;
-      if (tid == 0) { dropped[j] = 1; any = 1; }
-    } else {
-      const double r = sqrt(piv);
-      const double inv = 1.0 / r;
-      for (int c = j + 1 + tid; c < K; c += NT) L[j * K + c] *= inv;
-      if (tid == 0) { L[j * K + j] = r; dropped[j] = 0; }
-      __syncthreads();
-      const int nrem = K - j - 1;
-      for (int idx = tid; idx < nrem * nrem; idx += NT) {
-        const int a = j + 1 + idx / nrem, c = j + 1 + idx % nrem;
-        if (c >= a) L[a * K + c] -= L[j * K + a] * L[j * K + c];
+    if (tid == 0) { piv[j] = drop ? 0.0 : pj; dropped[j] = drop ? 1 : 0; if (drop) any = 1; }
+    if (!drop) {
+      const double inv = 1.0 / pj;
+      // row j is read-only during this step: keep this thread's columns of it
+      // in registers so the loads and stores of the update can overlap
+      double lj[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = j + 1 + tx + 16 * q;
+        lj[q] = c < K ? L[j * ld + c] : 0.0;
+      }
+      for (int a = j + 1 + ty; a < K; a += 16) {
+        const double la = L[j * ld + a] * inv;
+        double* row = &L[a * ld];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int c = j + 1 + tx + 16 * q;
+          if (c < K && c >= a) row[c] -= la * lj[q];
+        }
       }
     }
     __syncthreads();
   }
   for (int idx = tid; idx < K * K; idx += NT) {
     const int a = idx / K, c = idx % K;
-    if (c < a) L[idx] = 0.0;
+    double& v = L[a * ld + c];
+    if (c < a || dropped[a]) v = 0.0;
+    else {
+      const double r = sqrt(piv[a]);
+      v = c == a ? r : v / r;
+    }
   }
   __syncthreads();
   return any != 0;
 }
 
 // In-place inverse of the upper-triangular matrix in L; rows marked in
-// `dropped` are treated as having a unit diagonal.
-__device__ void trinv_lds(double* L, int K, const int* dropped, double* y) {
+// `dropped` are treated as having a unit diagonal.  Column j of the inverse is
+// -X[0:j,0:j] R[0:j,j] / R[j,j]; each row's dot product is split over 16 lanes
+// and reduced with shuffles.
+__device__ void trinv_lds(double* L, int K, int ld, const int* dropped, double* y) {
   const int tid = threadIdx.x;
+  const int g = tid >> 4, lane = tid & 15;
   for (int j = 0; j < K; ++j) {
-    if (tid < j) y[tid] = L[tid * K + j];
+    if (tid < j) y[tid] = L[tid * ld + j];
     __syncthreads();
-    const double djj = dropped[j] ? 1.0 : L[j * K + j];
+    const double djj = dropped[j] ? 1.0 : L[j * ld + j];
     const double ajj = 1.0 / djj;
-    if (tid < j) {
+    for (int i = g; i < j; i += 16) {
       double x = 0.0;
-      for (int k = tid; k < j; ++k) x += L[tid * K + k] * y[k];
-      L[tid * K + j] = -x * ajj;
+      for (int k = i + lane; k < j; k += 16) x += L[i * ld + k] * y[k];
+      x += __shfl_xor(x, 8, 16);
+      x += __shfl_xor(x, 4, 16);
+      x += __shfl_xor(x, 2, 16);
+      x += __shfl_xor(x, 1, 16);
+      if (lane == 0) L[i * ld + j] = -x * ajj;
     }
-    if (tid == 0) L[j * K + j] = ajj;
+    if (tid == 0) L[j * ld + j] = ajj;
     __syncthreads();
   }
 }
 
+// sweep 1: G -> R1, Ri1 = R1^{-1}.  sweep 2: G2 -> R2 (rows of vanishing
+// pivots dropped), R2i = inverse of R2 with unit diagonal on dropped rows.
 __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ args, int sweep,
                                                   GlobalState* st) {
-  __shared__ double L[KMAX * KMAX];
+  __shared__ double L[KMAX * (KMAX + 1)];
   __shared__ double red[NT];
   __shared__ double y[KMAX];
+  __shared__ double piv[KMAX];
   __shared__ int dropped[KMAX];
   const SmallArgs& a = args[blockIdx.x];
-  const int K = a.K;
+  const int K = a.K, ld = K + 1;
   const int tid = threadIdx.x;
   const double* Gin = sweep == 1 ? a.G : a.G2;
-  for (int i = tid; i < K * K; i += NT) L[i] = Gin[i];
+  for (int i = tid; i < K * K; i += NT) L[(i / K) * ld + i % K] = Gin[i];
   for (int i = tid; i < K; i += NT) dropped[i] = 0;
   __syncthreads();
   double md = 0.0;
   bool bad = false;
   for (int i = tid; i < K; i += NT) {
-    const double v = L[i * K + i];
+    const double v = L[i * ld + i];
     if (!isfinite(v)) bad = true; else md = fmax(md, v);
   }
-  for (int i = tid; i < K * K; i += NT) if (!isfinite(L[i])) bad = true;
+  for (int i = tid; i < K * K; i += NT) if (!isfinite(Gin[i])) bad = true;
   const double maxd = block_max(md, red);
   const double badany = block_max(bad ? 1.0 : 0.0, red);
   if (badany > 0.0 && tid == 0) atomicOr(&st->flags, 2u);
   const double tol = maxd > 0.0 ? a.tol_rel * maxd : 1.0;
-  const bool ev = chol_lds(L, K, tol, sweep, dropped);
-
-  if (sweep == 1) {
-    for (int i = tid; i < K * K; i += NT) a.R1[i] = L[i];
-    __syncthreads();
-    trinv_lds(L, K, dropped, y);
-    for (int i = tid; i < K * K; i += NT) a.Ri1[i] = L[i];
-    return;
-  }
-  if (ev && tid == 0) atomicOr(&st->flags, 1u);
-  // R = R2 R1 (both upper triangular), written unnormalised first
-  double mx = 0.0;
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int i = idx / K, c = idx % K;
-    double v = 0.0;
-    if (c >= i)
-      for (int k = i; k <= c; ++k) v += L[i * K + k] * a.R1[k * K + c];
-    a.R[idx] = v;
-    mx = fmax(mx, fabs(v));
-  }
-  const double gmx = block_max(mx, red);
-  const int e = exp2_of(gmx);
+  const bool ev = chol_lds(L, K, ld, tol, sweep, dropped, piv);
+  double* Rout = sweep == 1 ? a.R1 : a.R2;
+  double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
+  for (int i = tid; i < K * K; i += NT) Rout[i] = L[(i / K) * ld + i % K];
   __syncthreads();
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const double v = ldexp(a.R[idx], -e);
-    a.R[idx] = v;
-    if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[idx] = (float)v;
-    else reinterpret_cast<double*>(a.Rf)[idx] = v;
-  }
-  // Ri = R1^{-1} R2^{-1}
-  trinv_lds(L, K, dropped, y);
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int i = idx / K, c = idx % K;
-    double v = 0.0;
-    if (c >= i)
-      for (int k = i; k <= c; ++k) v += a.Ri1[i * K + k] * L[k * K + c];
-    a.Ri[idx] = v;
+  trinv_lds(L, K, ld, dropped, y);
+  for (int i = tid; i < K * K; i += NT) Riout[i] = L[(i / K) * ld + i % K];
+  if (sweep == 2 && ev && tid == 0) atomicOr(&st->flags, 1u);
+}
+
+// R (= R2 R1, formed by a GEMM) is divided by 2^e, e the binary exponent of
+// max |R|; e is added to the scale exponent; Rf = R in the forward type.
+__global__ __launch_bounds__(NT) void finish_r_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
+  __shared__ double red[NT];
+  const SmallArgs& a = args[blockIdx.x];
+  const int K = a.K;
+  const int tid = threadIdx.x;
+  double mx = 0.0;
+  for (int i = tid; i < K * K; i += NT) mx = fmax(mx, fabs(a.R[i]));
+  const int e = exp2_of(block_max(mx, red));
+  for (int i = tid; i < K * K; i += NT) {
+    const double v = ldexp(a.R[i], -e);
+    a.R[i] = v;
+    if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[i] = (float)v;
+    else reinterpret_cast<double*>(a.Rf)[i] = v;
   }
   if (tid == 0 && e != 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->log2_scale), (unsigned long long)(long long)e);
 }
 
-// ------------------------------------------------------------------ Jacobi eigensolver
-// Circle (round-robin) ordering: Ke = K rounded up to even, Ke-1 rounds of
-// Ke/2 disjoint pairs; index >= K is a dummy.
-__device__ __forceinline__ int circle_pos(int i, int r, int Ke) {
-  return i == 0 ? 0 : 1 + ((i - 1 + r) % (Ke - 1));
-}
-
+// ------------------------------------------------------------------ symmetric eigensolver
+// Bhat_t Q_t = Q_t Sigma_t^2 (Section 3.3) for one node per workgroup:
+//  1. Householder reduction to tridiagonal form T = H^T Bhat H in LDS; the
+//     reflectors are kept in the node's scratch;
+//  2. implicit QL iterations with Wilkinson shifts on T: one thread runs the
+//     chain of plane rotations of a sweep, all threads then apply them to the
+//     rows of Z (one LDS read and write per rotation and row, carried in a
+//     register);
+//  3. back-transformation Q = H Z, one column of Z per thread;
+//  4. eigenvalues sorted descending (clipped at 0) with their columns.
+// Q is a product of reflectors and rotations, orthogonal to working precision.
 __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
-  __shared__ double L[KMAX * KMAX];
-  __shared__ double cs_c[KMAX / 2], cs_s[KMAX / 2];
-  __shared__ int pp[KMAX / 2], qq[KMAX / 2];
+  __shared__ double L[KMAX * (KMAX + 1)];
+  __shared__ double dg[KMAX], eo[KMAX], rc[KMAX], rs[KMAX], vv[KMAX], pp[KMAX];
   __shared__ double red[NT];
-  __shared__ int nrot;
   __shared__ int rankpos[KMAX];
+  __shared__ int sh_m, sh_lo, sh_iters;
   const SmallArgs& a = args[blockIdx.x];
-  const int K = a.K;
+  const int K = a.K, ld = K + 1;
   const int tid = threadIdx.x;
-  const int Ke = K + (K & 1);
-  const int npair = Ke / 2, nround = Ke - 1;
-  double* Ag = a.scratch;                 // A while V is in LDS
-  double* Vg = a.scratch + K * K;         // V while A is in LDS
-  double* CS = a.scratch + 2 * K * K;     // rotations of one sweep: nround x npair x 2
+  double* Vs = a.scratch;                 // reflector k: Vs[k*K + i], i < K-k-1
+  double* Ts = a.scratch + K * K;         // tau_k
 
-  for (int i = tid; i < K * K; i += NT) {
-    L[i] = a.Bh[i];
-    Vg[i] = (i / K == i % K) ? 1.0 : 0.0;
+  for (int i = tid; i < K * K; i += NT) L[(i / K) * ld + i % K] = a.Bh[i];
+  __syncthreads();
+
+  // ---- 1. tridiagonalisation: for column k, reflect rows/cols k+1..K-1
+  for (int k = 0; k + 2 < K; ++k) {
+    const int m = K - k - 1;
+    double part = 0.0;
+    for (int i = tid; i < m; i += NT) { const double x = L[(k + 1 + i) * ld + k]; part += x * x; }
+    const double nrm2 = block_sum(part, red);
+    const double x0 = L[(k + 1) * ld + k];
+    double tau = 0.0, alpha = x0;
+    if (nrm2 > 0.0) {
+      alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+      tau = 1.0 / (alpha * (alpha - x0));
+    }
+    for (int i = tid; i < m; i += NT) vv[i] = i == 0 ? x0 - alpha : L[(k + 1 + i) * ld + k];
+    if (tid == 0) { dg[k] = L[k * ld + k]; eo[k] = alpha; Ts[k] = tau; }
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) Vs[k * K + i] = vv[i];
+    if (tau != 0.0) {
+      // p = tau A' v over the trailing block A' = L[k+1.., k+1..]
+      for (int i = tid; i < m; i += NT) {
+        double acc = 0.0;
+        const double* row = &L[(k + 1 + i) * ld + k + 1];
+        for (int j = 0; j < m; ++j) acc += row[j] * vv[j];
+        pp[i] = tau * acc;
+      }
+      __syncthreads();
+      double pv = 0.0;
+      for (int i = tid; i < m; i += NT) pv += pp[i] * vv[i];
+      const double beta = 0.5 * tau * block_sum(pv, red);
+      for (int i = tid; i < m; i += NT) pp[i] -= beta * vv[i];   // w = p - beta v
+      __syncthreads();
+      // A' <- A' - v w^T - w v^T
+      const int ty = tid >> 4, tx = tid & 15;
+      for (int i = ty; i < m; i += 16) {
+        const double vi = vv[i], wi = pp[i];
+        double* row = &L[(k + 1 + i) * ld + k + 1];
+        for (int j = tx; j < m; j += 16) row[j] -= vi * pp[j] + wi * vv[j];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (K >= 2) {
+      dg[K - 2] = L[(K - 2) * ld + K - 2];
+      eo[K - 2] = L[(K - 1) * ld + K - 2];
+    }
+    dg[K - 1] = L[(K - 1) * ld + K - 1];
+    eo[K - 1] = 0.0;
+    sh_iters = 0;
   }
   __syncthreads();
-  double fs = 0.0;
-  for (int i = tid; i < K * K; i += NT) fs += L[i] * L[i];
-  const double normA = sqrt(block_sum(fs, red));
-  const double floor_abs = 1e-18 * normA;
+  // QL converges at the top of the matrix and keeps the relative accuracy of
+  // small eigenvalues only if the tridiagonal grows toward the bottom.
+  // Gramians next to the root are graded the other way (large at the top):
+  // then T is reversed, T' = P T P, and Z starts as P so that Z = P Z'.
+  const bool rev = K > 1 && fabs(dg[0]) > fabs(dg[K - 1]);
+  double dtmp = 0.0, etmp = 0.0;
+  if (rev) {
+    if (tid < K) dtmp = dg[K - 1 - tid];
+    if (tid < K - 1) etmp = eo[K - 2 - tid];
+  }
+  __syncthreads();
+  if (rev) {
+    if (tid < K) dg[tid] = dtmp;
+    if (tid < K - 1) eo[tid] = etmp;
+  }
+  for (int i = tid; i < K * K; i += NT) {
+    const int r = i / K, c = i % K;
+    L[r * ld + c] = (rev ? (r + c == K - 1) : (r == c)) ? 1.0 : 0.0;
+  }
+  __syncthreads();
 
-  for (int sweep = 0; sweep < 40 && K > 1; ++sweep) {
-    if (tid == 0) nrot = 0;
-    __syncthreads();
-    for (int r = 0; r < nround; ++r) {
-      if (tid < npair) {
-        int p = circle_pos(tid, r, Ke), q = circle_pos(Ke - 1 - tid, r, Ke);
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < K) {
-          const double app = L[p * K + p], aqq = L[q * K + q], apq = L[p * K + q];
-          if (fabs(apq) > floor_abs && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            atomicAdd(&nrot, 1);
+  // ---- 2. implicit QL on (dg, eo), eo[i] couples i and i+1.  e_m deflates
+  // when it is below u (|d_m| + |d_m+1|) or below 1e-18 ||T|| (the rounding
+  // level of the Gramian: it moves no eigenvalue by more than that)
+  double tloc = 0.0;
+  for (int i = tid; i < K; i += NT) tloc = fmax(tloc, fabs(dg[i]) + fabs(eo[i]));
+  const double tnorm = block_max(tloc, red);
+  const double abs_tol = 1e-18 * tnorm;
+  for (int l = 0; l < K; ++l) {
+    for (int iter = 0; iter < 80; ++iter) {
+      if (tid == 0) sh_m = K - 1;
+      __syncthreads();
+      for (int m = l + tid; m < K - 1; m += NT) {
+        const double e = fabs(eo[m]);
+        if (e <= 2.2e-16 * (fabs(dg[m]) + fabs(dg[m + 1])) || e <= abs_tol) atomicMin(&sh_m, m);
+      }
+      __syncthreads();
+      const int m = sh_m;
+      __syncthreads();   // every wave has read sh_m before thread 0 may reset it
+      if (m == l) break;
+      if (tid == 0) {
+        double g = (dg[l + 1] - dg[l]) / (2.0 * eo[l]);
+        double r = sqrt(g * g + 1.0);
+        g = dg[m] - dg[l] + eo[l] / (g + (g >= 0.0 ? r : -r));
+        double sn = 1.0, cs = 1.0, p = 0.0;
+        double d_i1 = dg[m];                 // dg[i+1] for i = m-1
+        double e_i = eo[m - 1], d_i = dg[m - 1];
+        int i = m - 1;
+        for (; i >= l; --i) {
+          // operands of the next rotation, loaded ahead of the dependent chain
+          const double e_n = i > l ? eo[i - 1] : 0.0, d_n = i > l ? dg[i - 1] : 0.0;
+          const double f = sn * e_i, b = cs * e_i;
+          r = sqrt(f * f + g * g);
+          eo[i + 1] = r;
+          if (r == 0.0) {  // split: restart on the smaller block
+            dg[i + 1] = d_i1 - p;
+            eo[m] = 0.0;
+            break;
           }
-        } else {
-          q = p;  // dummy pair: identity
+          const double ir = 1.0 / r;
+          sn = f * ir;
+          cs = g * ir;
+          g = d_i1 - p;
+          r = (d_i - g) * sn + 2.0 * cs * b;
+          p = sn * r;
+          dg[i + 1] = g + p;
+          g = cs * r - b;
+          rc[i] = cs;
+          rs[i] = sn;
+          d_i1 = d_i;
+          e_i = e_n;
+          d_i = d_n;
         }
-        pp[tid] = p; qq[tid] = q; cs_c[tid] = c; cs_s[tid] = s;
-        CS[(r * npair + tid) * 2] = c;
-        CS[(r * npair + tid) * 2 + 1] = s;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = tid; idx < npair * K; idx += NT) {
-        const int j = idx / K, k = idx % K;
-        const double c = cs_c[j], s = cs_s[j];
-        if (s != 0.0) {
-          const int p = pp[j], q = qq[j];
-          const double x = L[p * K + k], yv = L[q * K + k];
-          L[p * K + k] = c * x - s * yv;
-          L[q * K + k] = s * x + c * yv;
+        sh_lo = i + 1;   // rotations i = m-1 .. lo were formed
+        if (i < l) {
+          dg[l] = d_i1 - p;
+          eo[l] = g;
+          eo[m] = 0.0;
         }
+        sh_iters += 1;
       }
       __syncthreads();
-      // columns: A <- A J
-      for (int idx = tid; idx < npair * K; idx += NT) {
-        const int k = idx / npair, j = idx % npair;
-        const double c = cs_c[j], s = cs_s[j];
-        if (s != 0.0) {
-          const int p = pp[j], q = qq[j];
-          const double x = L[k * K + p], yv = L[k * K + q];
-          L[k * K + p] = c * x - s * yv;
-          L[k * K + q] = s * x + c * yv;
-        }
-      }
-      __syncthreads();
-      if (tid < npair && cs_s[tid] != 0.0) {
-        L[pp[tid] * K + qq[tid]] = 0.0;
-        L[qq[tid] * K + pp[tid]] = 0.0;
-      }
-      __syncthreads();
-    }
-    const int rot = nrot;
-    __syncthreads();
-    if (rot == 0) break;
-    // apply this sweep's rotations to V (V <- V J), V swapped into LDS
-    for (int i = tid; i < K * K; i += NT) { Ag[i] = L[i]; L[i] = Vg[i]; }
-    __syncthreads();
-    for (int r = 0; r < nround; ++r) {
-      if (tid < npair) {
-        int p = circle_pos(tid, r, Ke), q = circle_pos(Ke - 1 - tid, r, Ke);
-        if (p > q) { int t = p; p = q; q = t; }
-        if (q >= K) q = p;
-        pp[tid] = p; qq[tid] = q;
-        cs_c[tid] = CS[(r * npair + tid) * 2];
-        cs_s[tid] = CS[(r * npair + tid) * 2 + 1];
-      }
-      __syncthreads();
-      for (int idx = tid; idx < npair * K; idx += NT) {
-        const int k = idx / npair, j = idx % npair;
-        const double c = cs_c[j], s = cs_s[j];
-        if (s != 0.0) {
-          const int p = pp[j], q = qq[j];
-          const double x = L[k * K + p], yv = L[k * K + q];
-          L[k * K + p] = c * x - s * yv;
-          L[k * K + q] = s * x + c * yv;
+      const int lo = sh_lo;
+      if (lo <= m - 1) {
+        for (int k = tid; k < K; k += NT) {
+          double* row = &L[k * ld];
+          double carry = row[m];
+          for (int i = m - 1; i >= lo; --i) {
+            const double x = row[i];
+            row[i + 1] = rs[i] * x + rc[i] * carry;
+            carry = rc[i] * x - rs[i] * carry;
+          }
+          row[lo] = carry;
         }
       }
       __syncthreads();
     }
-    for (int i = tid; i < K * K; i += NT) { Vg[i] = L[i]; L[i] = Ag[i]; }
+  }
+
+  // ---- 3. Q = H_0 H_1 ... H_{K-3} Z
+  for (int k = K - 3; k >= 0; --k) {
+    const int m = K - k - 1;
+    for (int i = tid; i < m; i += NT) vv[i] = Vs[k * K + i];
+    __syncthreads();
+    const double tau = Ts[k];
+    if (tau != 0.0) {
+      for (int j = tid; j < K; j += NT) {
+        double y = 0.0;
+        for (int i = 0; i < m; ++i) y += vv[i] * L[(k + 1 + i) * ld + j];
+        y *= tau;
+        for (int i = 0; i < m; ++i) L[(k + 1 + i) * ld + j] -= y * vv[i];
+      }
+    }
     __syncthreads();
   }
-  // sort eigenvalues descending (stable), write Q and lam
+
+  // ---- 4. sort descending (stable), write Q and lam
   for (int i = tid; i < K; i += NT) {
-    const double li = L[i * K + i];
+    const double li = dg[i];
     int pos = 0;
     for (int j = 0; j < K; ++j) {
-      const double lj = L[j * K + j];
+      const double lj = dg[j];
       if (lj > li || (lj == li && j < i)) ++pos;
     }
     rankpos[i] = pos;
     a.lam[pos] = fmax(li, 0.0);
     if (!isfinite(li)) atomicOr(&st->flags, 2u);
   }
+  if (tid == 0) atomicMax(&st->pad, min(sh_iters / K, 255));
   __syncthreads();
   for (int idx = tid; idx < K * K; idx += NT) {
     const int k = idx / K, i = idx % K;
-    a.Q[k * K + rankpos[i]] = Vg[k * K + i];
+    a.Q[k * K + rankpos[i]] = L[k * ld + i];
   }
 }
 
@@ -440,7 +525,7 @@ __global__ void root_norm_kernel(const double* BD, int K1, int K2, GlobalState* 
 __global__ void write_scale_kernel(const GlobalState* st, long long* out, unsigned int* flags,
                                    int* root_rank, int add_eD) {
   if (out) *out = st->log2_scale + (add_eD ? st->e_D : 0);
-  if (flags) *flags = st->flags;
+  if (flags) *flags = st->flags | ((unsigned)min(st->pad, 255) << 8);
   if (root_rank) *root_rank = 1;
 }
 
@@ -476,6 +561,12 @@ hipError_t launch_set_state(GlobalState* st, long long scale0, hipStream_t s) {
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(chol_kernel, dim3(n), dim3(NT), 0, s, args, sweep, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finish_r_kernel, dim3(n), dim3(NT), 0, s, args, st);
   return hipGetLastError();
 }
 

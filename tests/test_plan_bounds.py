@@ -73,8 +73,8 @@ def test_truncate_plans_in_bounds(L, case):
 def test_truncate_plans_nonuniform_ranks(L):
     import numpy as np
     rng = np.random.default_rng(3)
-    for trial in range(30):
-        d = int(rng.integers(2, 12))
+    for trial in range(40):
+        d = int(rng.integers(2, 18))
         nn = 2 * d - 1
         ns = [int(x) for x in rng.integers(1, 300, size=d)]
         xs = []
