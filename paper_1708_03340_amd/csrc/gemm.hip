@@ -98,16 +98,21 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
     const int64_t sAk = D.nseg > 0 ? D.segAk[s] : D.sAk;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      // loads go to a clamped in-range address and the value is multiplied
+      // by a 0/1 mask: a guarded load (or a select on its value) is compiled
+      // into a branch that waits for the load before the next one is issued.
+      // A clamped element only meets the mask outside the valid range of the
+      // output or on a k index whose true term is in the sum anyway, so a
+      // non-finite input still reaches every valid output it belongs to.
       const int gm = tm * BM + a_r[i], gk = c.k0 + a_k[i];
-      if (D.kr) {
-        ra[i] = (gm < M && gk < ks)
-                    ? (TM)(D.krY1[(int64_t)gm * D.krld1 + gk / D.krK2] * D.krY2[(int64_t)gm * D.krld2 + gk % D.krK2])
-                    : (TM)0;
-      } else {
-        ra[i] = (gm < M && gk < ks) ? (TM)Ap[(int64_t)gm * D.sAm + (int64_t)gk * sAk] : (TM)0;
-      }
+      const int cm = min(gm, M - 1), ck = min(gk, ks - 1);
+      TM va;
+      if (D.kr) va = (TM)(D.krY1[(int64_t)cm * D.krld1 + ck / D.krK2] * D.krY2[(int64_t)cm * D.krld2 + ck % D.krK2]);
+      else va = (TM)Ap[(int64_t)cm * D.sAm + (int64_t)ck * sAk];
+      ra[i] = va * (TM)(gm < M && gk < ks);
       const int gn = tn * BN + b_c[i], gkb = c.k0 + b_k[i];
-      rb[i] = (gn < N && gkb < ks) ? (TM)Bp[(int64_t)gkb * D.sBk + (int64_t)gn * D.sBn] : (TM)0;
+      const TM vb = (TM)Bp[(int64_t)min(gkb, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn];
+      rb[i] = vb * (TM)(gn < N && gkb < ks);
     }
   };
   auto advance = [&](Cursor& c) {
@@ -287,13 +292,15 @@ __global__ __launch_bounds__(NT, 2) void gemm128_kernel(const GemmDesc* __restri
     for (int i = 0; i < 8; ++i) {
       const int r = aK ? a_r0 : a_r0 + i, k = aK ? a_k0 + i : a_k0;
       const int gm = tm * BT + r, gk = c.k0 + k;
-      ra[i] = (gm < M && gk < ks) ? (double)Ap[(int64_t)gm * D.sAm + (int64_t)gk * sAk] : 0.0;
+      const double va = (double)Ap[(int64_t)min(gm, M - 1) * D.sAm + (int64_t)min(gk, ks - 1) * sAk];
+      ra[i] = va * (double)(gm < M && gk < ks);   // clamped load, 0/1 mask
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int r = bK ? b_r0 : b_r0 + i, k = bK ? b_k0 + i : b_k0;
       const int gn = tn * BT + r, gk = c.k0 + k;
-      rb[i] = (gn < N && gk < ks) ? (double)Bp[(int64_t)gk * D.sBk + (int64_t)gn * D.sBn] : 0.0;
+      const double vb = (double)Bp[(int64_t)min(gk, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn];
+      rb[i] = vb * (double)(gn < N && gk < ks);
     }
   };
   auto advance = [&](Cursor& c) {
