@@ -375,9 +375,11 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
 std::string kernel_name(const Op& op) {
   auto tn = [](int t) { return t == F32 ? "float" : "double"; };
   switch (op.kind) {
-    case OP_GEMM:
+    case OP_GEMM:   // the template arguments of the kernel that launch_gemm picks
+      if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +
-             (op.g.math == MATH_F32 ? "float" : "double") + ">";
+             (op.g.math == MATH_F32 ? "float" : "double") + "," +
+             (op.g.math == MATH_F32 && op.g.acc64 ? "true" : "false") + ">";
     case OP_CHOL1: case OP_CHOL2: return "chol_kernel";
     case OP_FINISHR: return "finish_r_kernel";
     case OP_EIG: return "eig_kernel";

@@ -9,9 +9,9 @@
 //    float32 may be indefinite); the second sweep repairs R;
 //  * sweep 2 drops the rows whose pivot vanishes (rank-deficient frames such
 //    as those of the sum A + A) and flags them.
-// Every elimination step loads its part of the trailing matrix into
-// registers, updates it and stores it back, so one LDS round trip is paid
-// per step instead of one per element.
+// The factor and the inverse are both formed with the matrix held in
+// registers across all steps, so a step costs a few LDS reads and at most one
+// barrier instead of a round trip of the trailing matrix through LDS.
 #include "dense_util.h"
 
 namespace ht {
@@ -19,65 +19,78 @@ namespace {
 
 constexpr int NT = DNT;
 
-__shared__ double g_trash[NT];   // sink for the stores of out-of-range lanes
 
-// In-place Cholesky G = R^T R (upper triangle) in LDL^T form: rows stay
-// unscaled during the elimination and are divided by sqrt(pivot) at the end.
-// Thread (ty, tx) owns rows ty + 16i and columns tx + 16q of the trailing
-// block; 16 x 16 blocks wholly outside it or below its diagonal are skipped
-// on uniform conditions.  Loads use clamped in-range addresses without
-// guards (a guarded load compiles to a branch that waits for it); stores of
-// out-of-range lanes go to a per-thread trash slot instead of sitting behind a
-// branch, which would make every store wait for the previous one.
-__device__ bool chol_lds(double* L, int K, int ld, double tol, int sweep, int* dropped, double* piv) {
+// Thread (ty, tx) = (tid / 16, tid % 16) owns the entries (ty + 16i, tx + 16q)
+// of the upper block triangle q >= i of a KMAX x KMAX matrix: 36 values kept
+// in registers for the whole factorisation.
+//
+// Cholesky G = R^T R, right-looking in LDL^T form (rows stay unscaled and are
+// divided by sqrt(pivot) at the end).  Step j reads the pivot row j from a
+// double-buffered row in LDS, applies the rank-1 update to the whole register
+// tile and the owners of row j+1 publish it (to the row buffer and to L): one
+// barrier per step.  Entries of rows or columns that are already eliminated,
+// or that lie past K or below the diagonal, receive meaningless updates; they
+// never feed an entry that is still live and are never read.
+// sweep 1: a pivot <= tol is replaced by tol; sweep 2: its row is dropped
+// (dropped[j] = 1, zero row).  Returns true if a row was dropped.  On return
+// L holds the scaled R (zero below the diagonal and on dropped rows).
+__device__ bool chol_regs(double* L, int K, int ld, double tol, int sweep, int* dropped, double* piv,
+                          double (*rowbuf)[KMAX]) {
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   __shared__ int any;
+  double v[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int q = i; q < 8; ++q) {
+      const int a = ty + 16 * i, c = tx + 16 * q;
+      v[i][q] = (a < K && c < K) ? L[a * ld + c] : 0.0;
+    }
   if (tid == 0) any = 0;
-  __syncthreads();
+  if (ty == 0) {   // publish row 0
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rowbuf[0][tx + 16 * q] = v[0][q];
+  }
   for (int j = 0; j < K; ++j) {
-    double pj = L[j * ld + j];
+    __syncthreads();
+    const double* rb = rowbuf[j & 1];
+    double pj = rb[j];
     bool drop = false;
     if (!(pj > tol)) {
       if (sweep == 1) pj = tol; else drop = true;
     }
     if (tid == 0) { piv[j] = drop ? 0.0 : pj; dropped[j] = drop ? 1 : 0; if (drop) any = 1; }
-    const int n = K - j - 1;                 // trailing order
-    if (!drop && n > 0) {
-      const double inv = 1.0 / pj;
-      const double* rj = &L[j * ld + j + 1];
-      double* T = &L[(j + 1) * ld + j + 1];
+    if (!drop) {
+      const double inv = rcp_nr(pj);
       double lr[8], lc[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        lr[i] = rj[min(ty + 16 * i, n - 1)] * inv;
-        lc[i] = rj[min(tx + 16 * i, n - 1)];
-      }
-      // all loads of the step first, then all stores: the compiler cannot
-      // move a load above a store to the same array by itself
-      double v[8][8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int ac = min(ty + 16 * i, n - 1);
-#pragma unroll
-        for (int q = i; q < 8; ++q)
-          if (16 * q < n) v[i][q] = T[ac * ld + min(tx + 16 * q, n - 1)];
+        lr[i] = rb[ty + 16 * i] * inv;
+        lc[i] = rb[tx + 16 * i];
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int a = ty + 16 * i;
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int q = i; q < 8; ++q) {
-          if (16 * q < n) {
+        for (int q = i; q < 8; ++q) v[i][q] -= lr[i] * lc[q];
+    }
+    // publish row j+1 (after this step's update) into the other buffer and L
+    const int jn = j + 1;
+    if (jn < K && ty == (jn & 15)) {
+      const int ib = jn >> 4;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i == ib) {
+#pragma unroll
+          for (int q = i; q < 8; ++q) {
             const int c = tx + 16 * q;
-            const bool ok = a < n && c < n && c >= a;
-            *(ok ? &T[a * ld + c] : &g_trash[tid]) = v[i][q] - lr[i] * lc[q];
+            rowbuf[jn & 1][c] = v[i][q];
+            if (c < K) L[jn * ld + c] = v[i][q];
           }
         }
-      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int idx = tid; idx < K * K; idx += NT) {
     const int a = idx / K, c = idx % K;
     double& x = L[a * ld + c];
@@ -91,48 +104,51 @@ __device__ bool chol_lds(double* L, int K, int ld, double tol, int sweep, int* d
   return any != 0;
 }
 
-// In-place inverse of the upper-triangular matrix in L (rows marked in
-// `dropped` get a unit diagonal).  Column j of the inverse is
-// -X[0:j, 0:j] R[0:j, j] / R[j, j] with X the part already inverted; each row's
-// dot product is split over 16 lanes and reduced with shuffles.  y holds
-// column j of R zero-padded to KMAX, so the products need no guards.
-__device__ void trinv_lds(double* L, int K, int ld, const int* dropped, double* y) {
+// X = R^{-1} for the upper-triangular R in L (rows marked in `dropped` get a
+// unit diagonal), column by column: X[i][j] = -(sum_k X[i][k] R[k][j]) / R[j][j]
+// for i < j.  Thread (g, l) = (tid / 16, tid % 16) keeps X[g + 16m][l + 16p],
+// p >= m, in registers; entries not yet computed are zero, so the dot product
+// over its columns needs no masks.  The 16 lanes of a row group (one DPP row)
+// sum with DPP moves and the owner of column j stores the result: no
+// barriers.  X is written to Xout (K x K, row-major).
+__device__ void trinv_regs(const double* L, int K, int ld, const int* dropped, double* Xout) {
   const int tid = threadIdx.x;
-  const int g = tid >> 4, lane = tid & 15;
+  const int g = tid >> 4, l = tid & 15;
+  double x[8][8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int p = m; p < 8; ++p) x[m][p] = 0.0;
   for (int j = 0; j < K; ++j) {
-    if (tid < KMAX) y[tid] = tid < j ? L[min(tid, K - 1) * ld + j] : 0.0;
-    __syncthreads();
-    const double djj = dropped[j] ? 1.0 : L[j * ld + j];
-    const double ajj = 1.0 / djj;
-    double yk[8];
+    const int jb = j >> 4;
+    const double ajj = rcp_nr(dropped[j] ? 1.0 : L[j * ld + j]);
+    double r[8];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) yk[p] = y[lane + 16 * p];
-    double x[8];
+    for (int p = 0; p < 8; ++p) r[p] = L[min(l + 16 * p, K - 1) * ld + j];
+    const bool owner = l == (j & 15);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      x[m] = 0.0;
-      if (16 * m < j) {
-        const double* row = &L[min(g + 16 * m, K - 1) * ld];
+      if (m <= jb) {     // rows g + 16m < j exist only in blocks m <= j / 16
+        double s = 0.0;
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
-          if (16 * p < j) x[m] += row[min(lane + 16 * p, K - 1)] * yk[p];
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      if (16 * m < j) {
-        double s = x[m];
-        s += __shfl_xor(s, 8, 16);
-        s += __shfl_xor(s, 4, 16);
-        s += __shfl_xor(s, 2, 16);
-        s += __shfl_xor(s, 1, 16);
+        for (int p = m; p < 8; ++p)
+          if (p <= jb) s += x[m][p] * r[p];
+        s = row16_sum(s);
         const int i = g + 16 * m;
-        *((lane == 0 && i < j) ? &L[i * ld + j] : &g_trash[tid]) = -s * ajj;
+        const double xij = i < j ? -s * ajj : (i == j ? ajj : 0.0);
+#pragma unroll
+        for (int p = m; p < 8; ++p)
+          if (p == jb && owner) x[m][p] = xij;
       }
     }
-    if (tid == 0) L[j * ld + j] = ajj;
-    __syncthreads();
   }
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int i = g + 16 * m, k = l + 16 * p;
+      if (i < K && k < K) Xout[i * K + k] = p >= m ? x[m][p] : 0.0;
+    }
 }
 
 // sweep 1: G -> R1, Ri1 = R1^{-1}.  sweep 2: G2 -> R2 (rows of vanishing
@@ -140,8 +156,8 @@ __device__ void trinv_lds(double* L, int K, int ld, const int* dropped, double* 
 __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ args, int sweep,
                                                   GlobalState* st) {
   __shared__ double L[KMAX * (KMAX + 1)];
+  __shared__ double rowbuf[2][KMAX];
   __shared__ double red[NT / 64];
-  __shared__ double y[KMAX];
   __shared__ double piv[KMAX];
   __shared__ int dropped[KMAX];
   const SmallArgs& a = args[blockIdx.x];
@@ -165,13 +181,11 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const double badany = wg_max(bad ? 1.0 : 0.0, red);
   if (badany > 0.0 && tid == 0) atomicOr(&st->flags, 2u);
   const double tol = maxd > 0.0 ? a.tol_rel * maxd : 1.0;
-  const bool ev = chol_lds(L, K, ld, tol, sweep, dropped, piv);
+  const bool ev = chol_regs(L, K, ld, tol, sweep, dropped, piv, rowbuf);
   double* Rout = sweep == 1 ? a.R1 : a.R2;
   double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
   for (int i = tid; i < K * K; i += NT) Rout[i] = L[(i / K) * ld + i % K];
-  __syncthreads();
-  trinv_lds(L, K, ld, dropped, y);
-  for (int i = tid; i < K * K; i += NT) Riout[i] = L[(i / K) * ld + i % K];
+  trinv_regs(L, K, ld, dropped, Riout);
   if (sweep == 2 && ev && tid == 0) atomicOr(&st->flags, 1u);
 }
 

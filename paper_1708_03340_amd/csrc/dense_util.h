@@ -32,6 +32,42 @@ __device__ __forceinline__ double wg_max(double v, double* red) {
   return r;
 }
 
+// 1 / x from the hardware reciprocal refined by two Newton steps (within an
+// ulp or two of the correctly rounded quotient; x finite and nonzero).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// 1 / sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+// DPP move of a double within rows of 16 lanes (CTRL: a DPP control code).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row, returned to every lane of the row:
+// swap neighbours, swap pairs (quad permutations), then the half-row and
+// row mirrors join quads into eights and eights into sixteen.
+__device__ __forceinline__ double row16_sum(double s) {
+  s += dpp_f64<0xB1>(s);    // quad_perm [1,0,3,2]
+  s += dpp_f64<0x4E>(s);    // quad_perm [2,3,0,1]
+  s += dpp_f64<0x141>(s);   // row_half_mirror
+  s += dpp_f64<0x140>(s);   // row_mirror
+  return s;
+}
+
 // Binary exponent e with x = m 2^e, 0.5 <= m < 1 (0 for x = 0 or non-finite).
 __device__ __forceinline__ int exp2_of(double x) {
   if (!(x > 0.0) || !isfinite(x)) return 0;

@@ -24,14 +24,6 @@ constexpr int NT = DNT;
 
 __shared__ double g_trash[NT];   // sink for the stores of out-of-range lanes
 
-// 1 / sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-
 __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
   __shared__ double L[KMAX * (KMAX + 1)];
   __shared__ double dg[KMAX], eo[KMAX], rc[KMAX], rs[KMAX];
