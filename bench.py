@@ -176,9 +176,9 @@ def main():
     total_ms = sum(v["ms"] for v in by_kernel.values())
     kname, kd = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
     # math type of a GEMM kernel: third template argument of gemm_kernel<A,B,math,acc64>;
-    # gemm128_kernel<A,B> computes in float64
+    # gemm128_kernel<A,B> and gemm_sb_kernel<S,T> compute in float64
     math_t = None
-    if kname.startswith("gemm128_kernel"):
+    if kname.startswith("gemm128_kernel") or kname.startswith("gemm_sb_kernel"):
         math_t = "double"
     elif kname.startswith("gemm_kernel"):
         math_t = kname[kname.index("<") + 1:].rstrip(">").split(",")[2]

@@ -151,6 +151,35 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
     tiles128 += (long long)((d.M + 127) / 128) * ((d.N + 127) / 128) * d.nbatch;
   }
   if (tiles128 < 512) big = false;
+  // small x streamed: one operand at most 128 x 128 (whole reduction), the
+  // other long and contiguous along its free index
+  {
+    bool ok = math == MATH_F64 && mode == GEMM_STORE;
+    int swap = -1;
+    long long items = 0;
+    for (const auto& d : descs) {
+      int kt = 0;
+      if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
+      else kt = d.K;
+      if (d.kr || d.KB != 1 || kt < 1 || kt > 128) { ok = false; break; }
+      const long long nbt = d.nbatch;
+      const bool c0 = d.M <= 128 && d.sBn == 1 && d.N * nbt >= 256;   // S = A, T = B
+      const bool c1 = d.N <= 128 && d.sAm == 1 && d.M * nbt >= 256;   // S = B^T, T = A^T
+      const int want = c0 ? 0 : (c1 ? 1 : -1);
+      if (want < 0 || (swap >= 0 && want != swap)) { ok = false; break; }
+      swap = want;
+      const int ns = swap ? d.M : d.N;
+      items = std::max<long long>(items, (long long)((ns + 127) / 128) * d.nbatch);
+    }
+    if (ok) {
+      op.g.sb = true;
+      big = false;
+      op.g.sb_swap = swap == 1;
+      op.g.sb_wn = 1;
+      const long long per = (512 + (long long)descs.size() - 1) / (long long)descs.size();
+      op.g.sb_grid = (int)std::max<long long>(1, std::min(per, items));
+    }
+  }
   const int tile = big ? 128 : 64;
   int maxtiles = 0, maxbatch = 1, maxkt = 1;
   for (const auto& d : descs) {
@@ -376,6 +405,10 @@ std::string kernel_name(const Op& op) {
   auto tn = [](int t) { return t == F32 ? "float" : "double"; };
   switch (op.kind) {
     case OP_GEMM:   // the template arguments of the kernel that launch_gemm picks
+      if (op.g.sb) {
+        const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
+        return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + ">";
+      }
       if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +
              (op.g.math == MATH_F32 ? "float" : "double") + "," +
@@ -1656,6 +1689,12 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (g.nbatch > op.g.maxbatch) return fail(HT_EINVAL, "validator: batch " + w);
         const int tl = op.g.big ? 128 : 64;
         if (((g.M + tl - 1) / tl) * ((g.N + tl - 1) / tl) > op.g.maxtiles) return fail(HT_EINVAL, "validator: tiles " + w);
+        if (op.g.sb) {   // the streamed kernel holds the whole reduction and the small side in LDS
+          int kt = 0;
+          for (int sg = 0; sg < nseg; ++sg) kt += g.nseg > 0 ? g.segK[sg] : g.K;
+          if (g.KB != 1 || kt < 1 || kt > 128 || (op.g.sb_swap ? g.N : g.M) > 128)
+            return fail(HT_EINVAL, "validator: streamed GEMM shape " + w);
+        }
         for (int sg = 0; sg < nseg; ++sg) {
           const int ks = g.nseg > 0 ? g.segK[sg] : g.K;
           if (ks <= 0) continue;

@@ -147,7 +147,7 @@ __device__ void trinv_regs(const double* L, int K, int ld, const int* dropped, d
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int i = g + 16 * m, k = l + 16 * p;
-      if (i < K && k < K) Xout[i * K + k] = p >= m ? x[m][p] : 0.0;
+      if (i < K && k < K) gst(&Xout[i * K + k], p >= m ? x[m][p] : 0.0);
     }
 }
 
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const double* Gin = sweep == 1 ? a.G : a.G2;
   bool bad = false;
   for (int i = tid; i < K * K; i += NT) {
-    const double v = Gin[i];
+    const double v = gld(&Gin[i]);
     if (!isfinite(v)) bad = true;
     L[(i / K) * ld + i % K] = v;
   }
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const bool ev = chol_regs(L, K, ld, tol, sweep, dropped, piv, rowbuf);
   double* Rout = sweep == 1 ? a.R1 : a.R2;
   double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
-  for (int i = tid; i < K * K; i += NT) Rout[i] = L[(i / K) * ld + i % K];
+  for (int i = tid; i < K * K; i += NT) gst(&Rout[i], L[(i / K) * ld + i % K]);
   trinv_regs(L, K, ld, dropped, Riout);
   if (sweep == 2 && ev && tid == 0) atomicOr(&st->flags, 1u);
 }

@@ -1,18 +1,23 @@
 // Symmetric eigensolver of the reduced Gramians: Bhat_t Q_t = Q_t Sigma_t^2
-// (Section 3.3), one workgroup per tree node, the K x K matrix in LDS
-// (K <= 128, row stride K + 1).
-//  1. Householder reduction to tridiagonal form T = H^T Bhat H; the
-//     reflectors are kept in the node's scratch.  Each step's matrix-vector
-//     product and rank-2 update load their register tile, compute and store.
-//  2. Implicit QL iterations with Wilkinson shifts on T.  One thread runs the
-//     chain of plane rotations of a sweep (rotation from one reciprocal square
-//     root, operands loaded one rotation ahead); all threads then apply the
-//     sweep to the rows of Z, eight columns per LDS round trip.  A tridiagonal
-//     that is graded large-at-the-top is reversed first (T' = P T P, Z starts
-//     as P): QL keeps the relative accuracy of small eigenvalues only when the
-//     matrix grows toward the bottom, and the Gramians next to the root are
-//     graded the other way.
-//  3. Back-transformation Q = H Z, two threads per column.
+// (Section 3.3), one workgroup of 256 threads per tree node, K <= 128.
+//
+//  1. Householder reduction to tridiagonal form T = H^T Bhat H with the matrix
+//     in registers (thread (ty, tx) holds rows ty + 16i, columns tx + 16q).
+//     A step publishes column k through LDS, forms p = tau A v with DPP sums
+//     along the 16 lanes of a row group, and applies the rank-2 update in
+//     registers: three barriers per step.  The reflectors go to the node's
+//     scratch.
+//  2. Implicit QL iterations with Wilkinson shifts on T, pipelined: wave 0
+//     finds the next unreduced block and runs the chain of plane rotations of
+//     the next sweep (one lane; rotation from a reciprocal square root refined
+//     by one third-order step), while waves 1-3 apply the previous sweep to
+//     the rows of Z in LDS.  One barrier per sweep.  A tridiagonal graded
+//     large-at-the-top is reversed first (T' = P T P, Z starts as P): QL keeps
+//     the relative accuracy of small eigenvalues only when the matrix grows
+//     toward the bottom, and the Gramians next to the root are graded the
+//     other way.
+//  3. Back-transformation Q = H_0 ... H_{K-3} Z with Z in registers, the 16
+//     lanes of a DPP row holding the rows of a column strip: no barriers.
 //  4. Eigenvalues sorted descending (clipped at 0) with their columns.
 // Q is a product of reflectors and rotations, orthogonal to working precision.
 #include "dense_util.h"
@@ -24,110 +29,136 @@ constexpr int NT = DNT;
 
 __shared__ double g_trash[NT];   // sink for the stores of out-of-range lanes
 
+// 1 / sqrt(x), x > 0 normal: hardware estimate (relative error ~5e-8) and one
+// third-order step, y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt3(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+// Sum over a wave of 64 lanes, returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+enum : int { SWEEP_NONE = 0, SWEEP_ROT = 1, SWEEP_DONE = 2 };
+
 __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
-  __shared__ double L[KMAX * (KMAX + 1)];
-  __shared__ double dg[KMAX], eo[KMAX], rc[KMAX], rs[KMAX];
-  __shared__ double vv[KMAX + 16], pp[KMAX + 16];   // zero beyond the active length
-  __shared__ double red[NT / 64];
+  __shared__ double L[KMAX * (KMAX + 1)];       // Z during the QL phase
+  __shared__ double dg[KMAX], eo[KMAX];
+  __shared__ double rcs[2][KMAX], rss[2][KMAX];  // rotations of two sweeps
+  __shared__ int sw_state[2], sw_m[2], sw_lo[2];
+  __shared__ double xs[KMAX], ps[KMAX];
+  __shared__ double part[16];
   __shared__ int rankpos[KMAX];
-  __shared__ int sh_m, sh_lo, sh_iters;
+  __shared__ int sh_iters;
   const SmallArgs& a = args[blockIdx.x];
   const int K = a.K, ld = K + 1;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ty = tid >> 4, tx = tid & 15;
   double* Vs = a.scratch;                 // reflector k: Vs[k*K + i], i < K-k-1
   double* Ts = a.scratch + K * K;         // tau_k
 
-  for (int i = tid; i < K * K; i += NT) L[(i / K) * ld + i % K] = a.Bh[i];
-  __syncthreads();
-
-  // ---- 1. tridiagonalisation
-  for (int k = 0; k + 2 < K; ++k) {
-    const int m = K - k - 1;
-    const double xi = tid < m ? L[(k + 1 + tid) * ld + k] : 0.0;
-    const double nrm2 = wg_sum(xi * xi, red);
-    const double x0 = L[(k + 1) * ld + k];
-    double tau = 0.0, alpha = x0;
-    if (nrm2 > 0.0) {
-      alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
-      tau = 1.0 / (alpha * (alpha - x0));
-    }
-    if (tid < KMAX + 16) {
-      const double v = tid == 0 ? x0 - alpha : xi;   // xi = 0 beyond m
-      vv[tid] = v;
-      pp[tid] = 0.0;
-      if (tid < m) Vs[k * K + tid] = v;
-    }
-    if (tid == 0) { dg[k] = L[k * ld + k]; eo[k] = alpha; Ts[k] = tau; }
-    __syncthreads();
-    if (tau != 0.0) {
-      double* A = &L[(k + 1) * ld + k + 1];   // trailing block, order m
-      // p = tau A v, two threads per row; loads go to clamped addresses
-      // (vv is zero past m) so none of them sits behind a branch
-      {
-        const int r = tid >> 1, h = tid & 1;
-        const double* row = &A[min(r, m - 1) * ld];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // ---- 1. tridiagonalisation, A in registers
+  {
+    double A[8][8];
 #pragma unroll
-        for (int c0 = 0; c0 < 64; c0 += 4) {
-          if (c0 < m) {
-            const int c = h * 64 + c0;
-            s0 += row[min(c, m - 1)] * vv[c];
-            s1 += row[min(c + 1, m - 1)] * vv[c + 1];
-            s2 += row[min(c + 2, m - 1)] * vv[c + 2];
-            s3 += row[min(c + 3, m - 1)] * vv[c + 3];
-          }
-        }
-        double sum = (s0 + s1) + (s2 + s3);
-        sum += __shfl_xor(sum, 1, 64);
-        if (r < m && h == 0) pp[r] = tau * sum;
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = ty + 16 * i, c = tx + 16 * q;
+        A[i][q] = (r < K && c < K) ? gld(&a.Bh[r * K + c]) : 0.0;
       }
-      __syncthreads();
-      const double pv = tid < m ? pp[tid] * vv[tid] : 0.0;
-      const double beta = 0.5 * tau * wg_sum(pv, red);
-      if (tid < m) pp[tid] -= beta * vv[tid];   // w = p - beta v (zero past m)
-      __syncthreads();
-      // A <- A - v w^T - w v^T; thread (ty, tx) owns rows ty + 16i and
-      // columns tx + 16q, blocks outside the order-m block skipped uniformly
-      double va[8], wa[8], vc[8], wc[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        va[i] = vv[ty + 16 * i];
-        wa[i] = pp[ty + 16 * i];
-        vc[i] = vv[tx + 16 * i];
-        wc[i] = pp[tx + 16 * i];
-      }
-      // all loads first, then all stores (out-of-range lanes store to a
-      // trash slot, so no store sits behind a branch)
-      double t[8][8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const double* rowc = &A[min(ty + 16 * i, m - 1) * ld];
+    for (int k = 0; k + 2 < K; ++k) {
+      const int kb = k >> 4;
+      // publish column k below the diagonal, and the diagonal entry
+      if (tx == (k & 15)) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (16 * i < m && 16 * q < m) t[i][q] = rowc[min(tx + 16 * q, m - 1)];
+          if (q == kb) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int r = ty + 16 * i;
+              xs[r] = r > k ? A[i][q] : 0.0;
+              if (r == k) dg[k] = A[i][q];
+            }
+          }
       }
+      __syncthreads();
+      // every wave forms ||x||^2 itself (the same sum in the same order)
+      const double x0 = xs[k + 1];
+      const double nrm2 = wave_sum(xs[lane] * xs[lane] + xs[lane + 64] * xs[lane + 64]);
+      double tau = 0.0, alpha = x0;
+      if (nrm2 > 0.0) {
+        alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+        tau = 1.0 / (alpha * (alpha - x0));
+      }
+      if (tid == 0) { eo[k] = alpha; gst(&Ts[k], tau); }
+      if (tid > k && tid < K) gst(&Vs[k * K + tid - k - 1], tid == k + 1 ? x0 - alpha : xs[tid]);
+      if (tau != 0.0) {
+        // v (zero at indices <= k) at this thread's rows and columns
+        double vr[8], vc[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int r = ty + 16 * i;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int c = tx + 16 * q;
-          if (16 * i < m && 16 * q < m)
-            *((r < m && c < m) ? &A[r * ld + c] : &g_trash[tid]) = t[i][q] - va[i] * wc[q] - wa[i] * vc[q];
+        for (int i = 0; i < 8; ++i) {
+          const int r = ty + 16 * i, c = tx + 16 * i;
+          vr[i] = r == k + 1 ? x0 - alpha : xs[r];
+          vc[i] = c == k + 1 ? x0 - alpha : xs[c];
         }
+        // p = tau A v at this thread's rows, summed over the 16 lanes of the row group
+        double pr[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) s = fma(A[i][q], vc[q], s);
+          pr[i] = tau * row16_sum(s);
+        }
+        // v . p: partial over the 8 rows of the group, joined across groups in LDS
+        double vp = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vp = fma(vr[i], pr[i], vp);
+        if (tx == 0) {
+          part[ty] = vp;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) ps[ty + 16 * i] = pr[i];
+        }
+        __syncthreads();
+        double tot = 0.0;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) tot += part[g];
+        const double beta = 0.5 * tau * tot;
+        double wr[8], wc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int r = ty + 16 * i, c = tx + 16 * i;
+          wr[i] = r > k ? pr[i] - beta * vr[i] : 0.0;
+          wc[i] = c > k ? ps[c] - beta * vc[i] : 0.0;
+        }
+        // A <- A - v w^T - w v^T (entries with an index <= k are unchanged)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) A[i][q] -= vr[i] * wc[q] + wr[i] * vc[q];
       }
+      __syncthreads();   // xs, ps, part are reused by the next step
     }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (K >= 2) {
-      dg[K - 2] = L[(K - 2) * ld + K - 2];
-      eo[K - 2] = L[(K - 1) * ld + K - 2];
+    // the trailing 2 x 2 (or smaller) block
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = ty + 16 * i, c = tx + 16 * q;
+        if (K >= 2 && r == K - 2 && c == K - 2) dg[K - 2] = A[i][q];
+        if (K >= 2 && r == K - 1 && c == K - 2) eo[K - 2] = A[i][q];
+        if (r == K - 1 && c == K - 1) dg[K - 1] = A[i][q];
+      }
+    if (tid == 0) {
+      eo[K - 1] = 0.0;
+      sh_iters = 0;
+      sw_state[0] = sw_state[1] = SWEEP_NONE;
     }
-    dg[K - 1] = L[(K - 1) * ld + K - 1];
-    eo[K - 1] = 0.0;
-    sh_iters = 0;
   }
   __syncthreads();
   const bool rev = K > 1 && fabs(dg[0]) > fabs(dg[K - 1]);
@@ -151,22 +182,39 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
   // below u (|d_m| + |d_m+1|) or below 1e-18 ||T|| (the rounding level of the
   // Gramian, which moves no eigenvalue by more than that)
   double tloc = 0.0;
-  for (int i = tid; i < K; i += NT) tloc = fmax(tloc, fabs(dg[i]) + fabs(eo[i]));
-  const double tnorm = wg_max(tloc, red);
-  const double abs_tol = 1e-18 * tnorm;
-  for (int l = 0; l < K; ++l) {
-    for (int iter = 0; iter < 80; ++iter) {
-      if (tid == 0) sh_m = K - 1;
-      __syncthreads();
-      for (int m = l + tid; m < K - 1; m += NT) {
-        const double e = fabs(eo[m]);
-        if (e <= 2.2e-16 * (fabs(dg[m]) + fabs(dg[m + 1])) || e <= abs_tol) atomicMin(&sh_m, m);
+  if (wave == 0)
+    for (int i = lane; i < K; i += 64) tloc = fmax(tloc, fabs(dg[i]) + fabs(eo[i]));
+  for (int off = 32; off > 0; off >>= 1) tloc = fmax(tloc, __shfl_xor(tloc, off, 64));
+  const double abs_tol = 1e-18 * tloc;   // used by wave 0 only
+  int l = 0, iter = 0;                   // producer state (wave 0)
+  // Finds the next sweep and writes its rotations into buffer b (wave 0 only).
+  auto produce = [&](int b) {
+    while (true) {
+      if (l >= K) {
+        if (lane == 0) sw_state[b] = SWEEP_DONE;
+        return;
       }
-      __syncthreads();
-      const int m = __builtin_amdgcn_readfirstlane(sh_m);
-      __syncthreads();   // every wave has read sh_m before thread 0 may reset it
-      if (m == l) break;
-      if (tid == 0) {
+      int m = K - 1;
+      for (int base = l; base < K - 1; base += 64) {
+        const int idx = base + lane;
+        bool neg = false;
+        if (idx < K - 1) {
+          const double e = fabs(eo[idx]);
+          neg = e <= 2.2e-16 * (fabs(dg[idx]) + fabs(dg[idx + 1])) || e <= abs_tol;
+        }
+        const unsigned long long bal = __ballot(neg);
+        if (bal) {
+          m = base + __ffsll((long long)bal) - 1;
+          break;
+        }
+      }
+      if (m == l || iter >= 80) {   // converged (or given up on): next eigenvalue
+        ++l;
+        iter = 0;
+        continue;
+      }
+      ++iter;
+      if (lane == 0) {
         double g = (dg[l + 1] - dg[l]) / (2.0 * eo[l]);
         double r = sqrt(g * g + 1.0);
         g = dg[m] - dg[l] + eo[l] / (g + (g >= 0.0 ? r : -r));
@@ -177,7 +225,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
         for (; i >= l; --i) {
           // operands of the next rotation (unused after the last one)
           const double e_n = eo[max(i - 1, l)], d_n = dg[max(i - 1, l)];
-          const double f = sn * e_i, b = cs * e_i;
+          const double f = sn * e_i, bb = cs * e_i;
           const double x2 = f * f + g * g;
           if (x2 == 0.0) {  // split: restart on the smaller block
             eo[i + 1] = 0.0;
@@ -185,96 +233,116 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
             eo[m] = 0.0;
             break;
           }
-          const double ir = rsqrt_nr(x2);
+          const double ir = rsqrt3(x2);
           eo[i + 1] = x2 * ir;
           sn = f * ir;
           cs = g * ir;
           g = d_i1 - p;
-          r = (d_i - g) * sn + 2.0 * cs * b;
+          r = (d_i - g) * sn + 2.0 * cs * bb;
           p = sn * r;
           dg[i + 1] = g + p;
-          g = cs * r - b;
-          rc[i] = cs;
-          rs[i] = sn;
+          g = cs * r - bb;
+          rcs[b][i] = cs;
+          rss[b][i] = sn;
           d_i1 = d_i;
           e_i = e_n;
           d_i = d_n;
         }
-        sh_lo = i + 1;   // rotations i = m-1 .. lo were formed
         if (i < l) {
           dg[l] = d_i1 - p;
           eo[l] = g;
           eo[m] = 0.0;
         }
+        sw_m[b] = m;
+        sw_lo[b] = i + 1;   // rotations m-1 .. lo were formed
+        sw_state[b] = SWEEP_ROT;
         sh_iters += 1;
       }
-      __syncthreads();
-      const int lo = __builtin_amdgcn_readfirstlane(sh_lo);
-      if (lo <= m - 1) {
-        // rotations m-1 .. lo applied to each row of Z, eight per LDS round
-        // trip; loads are clamped to lo and invalid lanes of a chunk keep
-        // the carry unchanged
-        for (int kr = tid; kr < K; kr += NT) {
-          double* row = &L[kr * ld];
-          double carry = row[m];
-          for (int i = m - 1; i >= lo; i -= 8) {
-            double xv[8], cv[8], sv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int iu = max(i - u, lo);
-              xv[u] = row[iu];
-              cv[u] = rc[iu];
-              sv[u] = rs[iu];
-            }
-            double o[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              o[u] = sv[u] * xv[u] + cv[u] * carry;
-              const double nc = cv[u] * xv[u] - sv[u] * carry;
-              carry = i - u >= lo ? nc : carry;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) *(i - u >= lo ? &row[i - u + 1] : &g_trash[tid]) = o[u];
-          }
-          row[lo] = carry;
-        }
-      }
-      __syncthreads();
+      return;
     }
+  };
+  if (wave == 0) produce(0);
+  __syncthreads();
+  for (int b = 0;; b ^= 1) {
+    if (sw_state[b] == SWEEP_DONE) break;
+    if (wave == 0) {
+      produce(b ^ 1);
+    } else {
+      // apply sweep b: rotations m-1 .. lo to each row of Z, eight per LDS
+      // round trip; loads are clamped to lo and invalid lanes keep the carry
+      const int m = sw_m[b], lo = sw_lo[b];
+      const double* rc = rcs[b];
+      const double* rs = rss[b];
+      const int kr = tid - 64;
+      if (kr < K && lo <= m - 1) {
+        double* row = &L[kr * ld];
+        double carry = row[m];
+        for (int i = m - 1; i >= lo; i -= 8) {
+          double xv[8], cv[8], sv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int iu = max(i - u, lo);
+            xv[u] = row[iu];
+            cv[u] = rc[iu];
+            sv[u] = rs[iu];
+          }
+          double o[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            o[u] = sv[u] * xv[u] + cv[u] * carry;
+            const double nc = cv[u] * xv[u] - sv[u] * carry;
+            carry = i - u >= lo ? nc : carry;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) *(i - u >= lo ? &row[i - u + 1] : &g_trash[tid]) = o[u];
+        }
+        row[lo] = carry;
+      }
+    }
+    __syncthreads();
   }
 
-  // ---- 3. Q = H_0 H_1 ... H_{K-3} Z, two threads per column taking the
-  // even and odd rows of the reflector; vv is zero past m
-  for (int k = K - 3; k >= 0; --k) {
-    const int m = K - k - 1;
-    if (tid < KMAX + 16) vv[tid] = tid < m ? Vs[k * K + tid] : 0.0;
-    __syncthreads();
-    const double tau = Ts[k];
-    if (tau != 0.0) {
-      const int j = tid >> 1, h = tid & 1;
-      if (j < K) {
-        double* Z = &L[(k + 1) * ld + j];
-        double y = 0.0;
-        for (int i = h; i < m; i += 16) {
-          double zv[8];
+  // ---- 3. Q = H_0 H_1 ... H_{K-3} Z with Z in registers: thread (cg, rl) =
+  // (tid / 16, tid % 16) holds Z[rl + 16i][cg + 16q]; a DPP row is one column strip
+  const int rl = tid & 15, cg = tid >> 4;
+  double Z[8][8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) zv[u] = Z[min(i + 2 * u, m - 1) * ld];
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) y += vv[i + 2 * u] * zv[u];
-        }
-        y += __shfl_xor(y, 1, 64);
-        y *= tau;
-        for (int i = h; i < m; i += 16) {
-          double zv[8];
+    for (int q = 0; q < 8; ++q) {
+      const int r = rl + 16 * i, c = cg + 16 * q;
+      Z[i][q] = (r < K && c < K) ? L[r * ld + c] : 0.0;
+    }
+  if (K >= 3) {
+    double vn[8];
+    double taun = 0.0;
+    auto load_v = [&](int k) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) zv[u] = Z[min(i + 2 * u, m - 1) * ld];
+      for (int i = 0; i < 8; ++i) {
+        const int r = rl + 16 * i;
+        vn[i] = (r > k && r < K) ? gld(&Vs[k * K + r - k - 1]) : 0.0;
+      }
+      taun = gld(&Ts[k]);
+    };
+    load_v(K - 3);
+    for (int k = K - 3; k >= 0; --k) {
+      double v[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            *(i + 2 * u < m ? &Z[(i + 2 * u) * ld] : &g_trash[tid]) = zv[u] - y * vv[i + 2 * u];
+      for (int i = 0; i < 8; ++i) v[i] = vn[i];
+      const double tau = taun;
+      if (k > 0) load_v(k - 1);   // next reflector, in flight during this one
+      if (tau != 0.0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) s = fma(v[i], Z[i][q], s);
+          const double y = tau * row16_sum(s);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) Z[i][q] = fma(-v[i], y, Z[i][q]);
         }
       }
     }
-    __syncthreads();
   }
 
   // ---- 4. sort descending (stable), write Q and lam
@@ -286,15 +354,18 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
       if (lj > li || (lj == li && j < i)) ++pos;
     }
     rankpos[i] = pos;
-    a.lam[pos] = fmax(li, 0.0);
+    gst(&a.lam[pos], fmax(li, 0.0));
     if (!isfinite(li)) atomicOr(&st->flags, 2u);
   }
   if (tid == 0) atomicMax(&st->pad, min(sh_iters / K, 255));
   __syncthreads();
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int k = idx / K, i = idx % K;
-    a.Q[k * K + rankpos[i]] = L[k * ld + i];
-  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = rl + 16 * i, c = cg + 16 * q;
+      if (r < K && c < K) gst(&a.Q[r * K + rankpos[c]], Z[i][q]);
+    }
 }
 
 }  // namespace

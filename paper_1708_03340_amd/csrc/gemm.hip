@@ -107,11 +107,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
       const int gm = tm * BM + a_r[i], gk = c.k0 + a_k[i];
       const int cm = min(gm, M - 1), ck = min(gk, ks - 1);
       TM va;
-      if (D.kr) va = (TM)(D.krY1[(int64_t)cm * D.krld1 + ck / D.krK2] * D.krY2[(int64_t)cm * D.krld2 + ck % D.krK2]);
-      else va = (TM)Ap[(int64_t)cm * D.sAm + (int64_t)ck * sAk];
+      if (D.kr) va = (TM)(gld(&D.krY1[(int64_t)cm * D.krld1 + ck / D.krK2]) * gld(&D.krY2[(int64_t)cm * D.krld2 + ck % D.krK2]));
+      else va = (TM)gld(&Ap[(int64_t)cm * D.sAm + (int64_t)ck * sAk]);
       ra[i] = va * (TM)(gm < M && gk < ks);
       const int gn = tn * BN + b_c[i], gkb = c.k0 + b_k[i];
-      const TM vb = (TM)Bp[(int64_t)min(gkb, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn];
+      const TM vb = (TM)gld(&Bp[(int64_t)min(gkb, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn]);
       rb[i] = vb * (TM)(gn < N && gkb < ks);
     }
   };
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
   }
 
   double alpha = D.alpha;
-  if (D.alpha_dev) alpha *= *D.alpha_dev;
+  if (D.alpha_dev) alpha *= gld(D.alpha_dev);
   char* Cb = reinterpret_cast<char*>(D.C);
   const int esz = tC == F64 ? 8 : 4;
   const int64_t coff_b = (int64_t)b * D.sCb;
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmDesc* __restrict__ d
           const int64_t off = coff_b + (int64_t)row * D.sCm + (int64_t)col * D.sCn;
           if (tC == F64) {
             double* p = reinterpret_cast<double*>(Cb) + off;
-            if (mode == GEMM_ATOMIC) atomicAdd(p, val); else *p = val;
+            if (mode == GEMM_ATOMIC) gatomic_add(p, val); else gst(p, val);
           } else {
             float* p = reinterpret_cast<float*>(Cb) + off;
-            if (mode == GEMM_ATOMIC) atomicAdd(p, (float)val); else *p = (float)val;
+            if (mode == GEMM_ATOMIC) gatomic_add(p, (float)val); else gst(p, (float)val);
           }
         }
       }
@@ -292,14 +292,14 @@ __global__ __launch_bounds__(NT, 2) void gemm128_kernel(const GemmDesc* __restri
     for (int i = 0; i < 8; ++i) {
       const int r = aK ? a_r0 : a_r0 + i, k = aK ? a_k0 + i : a_k0;
       const int gm = tm * BT + r, gk = c.k0 + k;
-      const double va = (double)Ap[(int64_t)min(gm, M - 1) * D.sAm + (int64_t)min(gk, ks - 1) * sAk];
+      const double va = (double)gld(&Ap[(int64_t)min(gm, M - 1) * D.sAm + (int64_t)min(gk, ks - 1) * sAk]);
       ra[i] = va * (double)(gm < M && gk < ks);   // clamped load, 0/1 mask
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int r = bK ? b_r0 : b_r0 + i, k = bK ? b_k0 + i : b_k0;
       const int gn = tn * BT + r, gk = c.k0 + k;
-      const double vb = (double)Bp[(int64_t)min(gk, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn];
+      const double vb = (double)gld(&Bp[(int64_t)min(gk, ks - 1) * D.sBk + (int64_t)min(gn, N - 1) * D.sBn]);
       rb[i] = vb * (double)(gn < N && gk < ks);
     }
   };
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(NT, 2) void gemm128_kernel(const GemmDesc* __restri
   }
 
   double alpha = D.alpha;
-  if (D.alpha_dev) alpha *= *D.alpha_dev;
+  if (D.alpha_dev) alpha *= gld(D.alpha_dev);
   char* Cb = reinterpret_cast<char*>(D.C);
   const int64_t coff_b = (int64_t)b * D.sCb;
 #pragma unroll
@@ -370,10 +370,10 @@ __global__ __launch_bounds__(NT, 2) void gemm128_kernel(const GemmDesc* __restri
           const int64_t off = coff_b + (int64_t)row * D.sCm + (int64_t)col * D.sCn;
           if (tC == F64) {
             double* p = reinterpret_cast<double*>(Cb) + off;
-            if (mode == GEMM_ATOMIC) atomicAdd(p, val); else *p = val;
+            if (mode == GEMM_ATOMIC) gatomic_add(p, val); else gst(p, val);
           } else {
             float* p = reinterpret_cast<float*>(Cb) + off;
-            if (mode == GEMM_ATOMIC) atomicAdd(p, (float)val); else *p = (float)val;
+            if (mode == GEMM_ATOMIC) gatomic_add(p, (float)val); else gst(p, (float)val);
           }
         }
       }
@@ -391,6 +391,7 @@ hipError_t go128(const GemmLaunch& g, hipStream_t s) {
 
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s) {
   if (g.ndesc <= 0 || g.maxtiles <= 0) return hipSuccess;
+  if (g.sb) return launch_gemm_sb(g, s);
   const bool a32 = g.tA == F32, b32 = g.tB == F32;
   if (g.big) {
     if (a32 && b32) return go128<float, float>(g, s);

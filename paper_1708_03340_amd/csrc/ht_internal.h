@@ -59,10 +59,35 @@ struct GemmLaunch {
   int splitk;              // blocks along the reduction (GEMM_ATOMIC if > 1)
   bool acc64;              // MATH_F32 only: float64 accumulation across k-slabs
   bool big;                // MATH_F64 only: 128 x 128 tiles
+  bool sb;                 // MATH_F64, GEMM_STORE: small operand in LDS, the other streamed
+  bool sb_swap;            //   small operand is B (A streamed along M)
+  int sb_grid;             //   workgroups per descriptor
+  int sb_wn;               //   16-column MFMA blocks per wave (2: 4 waves, else 8 waves)
   int ndesc, maxbatch, maxtiles;
   const GemmDesc* descs;   // device pointer
 };
+
+// Global-memory accesses made through the global address space.  Pointers
+// read from argument tables are generic, and generic (flat) loads also count
+// against the LDS wait counter: every wait for an LDS operand would then also
+// wait for the HBM loads in flight.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+__device__ __forceinline__ void gatomic_add(double* p, double v) {
+  __builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double*)p, v);
+}
+__device__ __forceinline__ void gatomic_add(float* p, float v) {
+  __builtin_amdgcn_global_atomic_fadd_f32((__attribute__((address_space(1))) float*)p, v);
+}
+
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t stream);
+hipError_t launch_gemm_sb(const GemmLaunch& g, hipStream_t stream);
 
 // ---------------------------------------------------------------- small dense kernels
 // Per-node argument block of the small dense kernels (device-resident table).
