@@ -175,25 +175,27 @@ def main():
         k["labels"].add(e["label"])
     total_ms = sum(v["ms"] for v in by_kernel.values())
     kname, kd = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
-    # math type of a GEMM kernel: third template argument of gemm_kernel<A,B,math,acc64>;
-    # gemm128_kernel<A,B> and gemm_sb_kernel<S,T> compute in float64
+    # math type of a GEMM kernel: third template argument of gemm_kernel<A,B,math,acc64>
+    # and gemm_rk_kernel<A,B,math,sym>; gemm128_kernel<A,B> and gemm_sb_kernel<S,T>
+    # compute in float64
     math_t = None
     if kname.startswith("gemm128_kernel") or kname.startswith("gemm_sb_kernel"):
         math_t = "double"
-    elif kname.startswith("gemm_kernel"):
+    elif kname.startswith("gemm_kernel") or kname.startswith("gemm_rk_kernel"):
         math_t = kname[kname.index("<") + 1:].rstrip(">").split(",")[2]
+    alg_bytes = kd["bytes"] / kd["launches"]
     if math_t in PEAKS:
         achieved = kd["flops"] / (kd["ms"] * 1e-3)
         roof = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAKS[math_t] / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAKS[math_t], traffic=measured_traffic(kname), kernel=kname,
                     avg_launch_us=kd["ms"] * 1e3 / kd["launches"], launches_per_step=kd["launches"] / args.steps,
-                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps))
+                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps), alg_bytes_per_launch=alg_bytes)
     else:
         achieved = kd["bytes"] / (kd["ms"] * 1e-3)
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=achieved / HBM_PEAK, traffic=measured_traffic(kname), kernel=kname,
                     avg_launch_us=kd["ms"] * 1e3 / kd["launches"], launches_per_step=kd["launches"] / args.steps,
-                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps))
+                    share_of_step=kd["ms"] / (t_mixed * 1e3 * args.steps), alg_bytes_per_launch=alg_bytes)
     if args.breakdown or True:
         labels = {}
         for e in prof:

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libht.so")
-SOURCES = ["gemm.hip", "gemm_sb.hip", "chol.hip", "eig.hip", "smallla.hip", "entries.hip", "capi.cpp"]
+SOURCES = ["gemm.hip", "gemm_sb.hip", "gemm_rk.hip", "chol.hip", "eig.hip", "smallla.hip", "entries.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HT_OFFLOAD_ARCH", "gfx950")

@@ -180,6 +180,27 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
       op.g.sb_grid = (int)std::max<long long>(1, std::min(per, items));
     }
   }
+  // long reductions into a result of at most 128 x 128, split over k
+  // (only the symmetric float64 Gram matrices: for the others the 64 x 64
+  // tiles are as fast)
+  if (mode == GEMM_ATOMIC && !op.g.sb && math == MATH_F64) {
+    bool ok = true, sym = tA == tB;
+    long long chunks = 0;
+    for (const auto& d : descs) {
+      if (d.kr || d.nseg > 0 || d.nbatch != 1 || d.M > 128 || d.N > 128 || d.M <= 64 || d.N <= 64 || d.K < 1 ||
+          !(d.sAk == 1 || d.sAm == 1) || !(d.sBk == 1 || d.sBn == 1)) { ok = false; break; }
+      if (!(d.A == d.B && d.M == d.N && d.sAm == d.sBn && d.sAk == d.sBk && d.sAkb == d.sBkb)) sym = false;
+      chunks = std::max<long long>(chunks, (long long)((d.K + 15) / 16) * d.KB);
+    }
+    if (ok && sym) {
+      op.g.rk = true;
+      op.g.rk_sym = sym;
+      op.g.rk_kc = 32;
+      const long long want = (1024 + (long long)descs.size() - 1) / (long long)descs.size();
+      op.g.rk_split = (int)std::max<long long>(1, std::min(want, (chunks + 15) / 16));
+      big = false;
+    }
+  }
   const int tile = big ? 128 : 64;
   int maxtiles = 0, maxbatch = 1, maxkt = 1;
   for (const auto& d : descs) {
@@ -407,7 +428,14 @@ std::string kernel_name(const Op& op) {
     case OP_GEMM:   // the template arguments of the kernel that launch_gemm picks
       if (op.g.sb) {
         const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
-        return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + ">";
+        return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + "," + std::to_string(op.g.sb_wn == 2 ? 2 : 1) +
+               ">";
+      }
+      if (op.g.rk) {
+        const std::string tm = op.g.math == MATH_F32 ? "float" : "double";
+        const int kc = op.g.rk_sym && op.g.rk_kc == 32 ? 32 : 16;
+        return std::string("gemm_rk_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," + tm + "," +
+               (op.g.rk_sym ? "true" : "false") + "," + std::to_string(kc) + ">";
       }
       if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +

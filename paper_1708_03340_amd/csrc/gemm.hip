@@ -392,6 +392,7 @@ hipError_t go128(const GemmLaunch& g, hipStream_t s) {
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s) {
   if (g.ndesc <= 0 || g.maxtiles <= 0) return hipSuccess;
   if (g.sb) return launch_gemm_sb(g, s);
+  if (g.rk) return launch_gemm_rk(g, s);
   const bool a32 = g.tA == F32, b32 = g.tB == F32;
   if (g.big) {
     if (a32 && b32) return go128<float, float>(g, s);

@@ -1,0 +1,228 @@
+// Long reductions with a small result,
+//   C[m][n] (+)= alpha * sum_k A[m][k] B[k][n],   m < M <= 128, n < N <= 128,
+// split over k between workgroups that add their partial results atomically:
+// the Gram matrices of both CholeskyQR2 sweeps (W^T W of the leaf frames and
+// M1(B') M1(B')^T of the transfer tensors, Section 3.4) and the son Gramians
+// of eqs. (acctransferSon1/2), reductions over 1e4 .. 1.6e4 terms.
+//
+// A workgroup owns the whole 128 x 128 result for its slice of k.  The slice
+// moves through LDS in 16-deep chunks (double-buffered, next chunk prefetched
+// into registers, one barrier per chunk), loaded along whichever index of
+// each operand is contiguous.  Fragments are read as four consecutive k per
+// lane: MFMA q of a 16-deep step then pairs k = 4j + q of A with the same k
+// of B in lane group j, so the four products cover the chunk exactly, with A
+// and B permuted alike.  When B is A^T of the same matrix (a Gram matrix)
+// only the 36 blocks of 16 x 16 on or above the diagonal are formed, each
+// wave taking block rows w and 7-w, and the off-diagonal blocks are added at
+// both places.
+#include "ht_internal.h"
+
+namespace ht {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int RK_NT = 256;
+
+template <typename TM> struct RkTraits;
+template <> struct RkTraits<double> {
+  using V = doublex4;
+  static constexpr int PAD = 2;   // row stride 18 doubles = 144 B (16-B aligned fragments)
+  __device__ static V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // FP64 16x16x4: register v of lane l holds row 4v + l/16
+  __device__ static int row(int v, int lane) { return 4 * v + (lane >> 4); }
+};
+template <> struct RkTraits<float> {
+  using V = floatx4;
+  static constexpr int PAD = 4;   // row stride 20 floats = 80 B
+  __device__ static V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // FP32 16x16x4: register v of lane l holds row 4(l/16) + v
+  __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename TA, typename TB, typename TM, bool SYM, int RK_KC>
+__global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __restrict__ descs, int nsplit,
+                                                          int tC, int mode) {
+  constexpr int LU = RK_KC / 2;   // elements per thread per operand and chunk
+  using Tr = RkTraits<TM>;
+  using V = typename Tr::V;
+  constexpr int LDK = RK_KC + Tr::PAD;
+  __shared__ TM As[2][128][LDK];
+  __shared__ TM Bs[SYM ? 1 : 2][SYM ? 1 : 128][LDK];
+
+  const GemmDesc& D = descs[blockIdx.y];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = D.M, N = D.N, K = D.K;
+  const int cpb = (K + RK_KC - 1) / RK_KC;          // chunks per reduction block
+  const int total = cpb * D.KB;
+  const int per = (total + nsplit - 1) / nsplit;
+  const int c0 = blockIdx.x * per, c1 = min(total, c0 + per);
+  if (c0 >= c1) return;
+
+  const bool a_kc = D.sAk == 1, b_kc = D.sBk == 1;
+  const TA* Ab = reinterpret_cast<const TA*>(D.A);
+  const TB* Bb = reinterpret_cast<const TB*>(D.B);
+
+  // loader coordinates: along k (thread t: row t/2, k (t%2)*LU .. +LU-1) or
+  // along the row index (thread t: k t/(128/LU), LU rows from (t%(128/LU))*LU)
+  constexpr int RG = 128 / LU;
+  TM ra[LU], rb[LU];
+  auto load = [&](int c) {
+    const int kb = c / cpb, k0 = (c % cpb) * RK_KC;
+    const TA* Ak = Ab + (int64_t)kb * D.sAkb;
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
+      const int k = a_kc ? k0 + (tid & 1) * LU + u : k0 + tid / RG;
+      const TM v = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]);
+      ra[u] = v * (TM)(k < K);
+    }
+    if (!SYM) {
+      const TB* Bk = Bb + (int64_t)kb * D.sBkb;
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int n = b_kc ? (tid >> 1) : (tid % RG) * LU + u;
+        const int k = b_kc ? k0 + (tid & 1) * LU + u : k0 + tid / RG;
+        const TM v = (TM)gld(&Bk[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]);
+        rb[u] = v * (TM)(k < K);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
+      const int k = a_kc ? (tid & 1) * LU + u : tid / RG;
+      As[buf][r][k] = ra[u];
+    }
+    if (!SYM) {
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int n = b_kc ? (tid >> 1) : (tid % RG) * LU + u;
+        const int k = b_kc ? (tid & 1) * LU + u : tid / RG;
+        Bs[buf][n][k] = rb[u];
+      }
+    }
+  };
+
+  // blocks of this wave: FULL: rows 4(w/2) + i, columns 4(w%2) + j;
+  // SYM: block rows w and 7-w against block columns on or right of them
+  constexpr int NA = SYM ? 2 : 4, NB = SYM ? 8 : 4;
+  V acc[NA][NB];
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = V{0, 0, 0, 0};
+  auto rowblk = [&](int i) { return SYM ? (i == 0 ? wave : 7 - wave) : 4 * (wave >> 1) + i; };
+  auto colblk = [&](int j) { return SYM ? j : 4 * (wave & 1) + j; };
+
+  load(c0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int c = c0; c < c1; ++c) {
+    const bool more = c + 1 < c1;
+    if (more) load(c + 1);
+    // four consecutive k of the lane's row per 16-deep step, k = 16s + 4 (lane / 16) + q,
+    // read in two halves of two to keep the fragment registers few
+#pragma unroll
+    for (int st = 0; st < RK_KC / 16; ++st) {
+      const int kq = 16 * st + 4 * (lane >> 4);
+#pragma unroll
+      for (int hq = 0; hq < 2; ++hq) {
+        TM fa[NA][2], fb[NB][2];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const TM* p = &As[buf][16 * rowblk(i) + (lane & 15)][kq + 2 * hq];
+          fa[i][0] = p[0];
+          fa[i][1] = p[1];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (SYM && j < wave) continue;   // block columns left of both rows
+          const TM* p = SYM ? &As[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq]
+                            : &Bs[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq];
+          fb[j][0] = p[0];
+          fb[j][1] = p[1];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              if (SYM && i == 1 && j < 4) continue;   // block row 7-w >= 4: never left of 4
+              if (SYM && colblk(j) < rowblk(i)) continue;
+              acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
+            }
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  double alpha = D.alpha;
+  if (D.alpha_dev) alpha *= gld(D.alpha_dev);
+  char* Cb = reinterpret_cast<char*>(D.C);
+  auto put = [&](int m, int n, double val) {
+    const int64_t off = (int64_t)m * D.sCm + (int64_t)n * D.sCn;
+    if (tC == F64) {
+      double* p = reinterpret_cast<double*>(Cb) + off;
+      if (mode == GEMM_ATOMIC) gatomic_add(p, val); else gst(p, val);
+    } else {
+      float* p = reinterpret_cast<float*>(Cb) + off;
+      if (mode == GEMM_ATOMIC) gatomic_add(p, (float)val); else gst(p, (float)val);
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int rbk = rowblk(i), cbk = colblk(j);
+      if (SYM && i == 1 && j < 4) continue;
+      if (SYM && cbk < rbk) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rbk + Tr::row(v, lane), n = 16 * cbk + (lane & 15);
+        if (m < M && n < N) {
+          const double val = alpha * (double)acc[i][j][v];
+          put(m, n, val);
+          if (SYM && cbk != rbk) put(n, m, val);
+        }
+      }
+    }
+}
+
+template <typename TA, typename TB, typename TM>
+hipError_t go_rk(const GemmLaunch& g, hipStream_t s) {
+  dim3 grid(g.rk_split, g.ndesc, 1);
+  if (g.rk_sym && g.rk_kc == 32)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, true, 32>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+  else if (g.rk_sym)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, true, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+  else
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, false, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+  return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t go_rk_types(const GemmLaunch& g, hipStream_t s) {
+  const bool a32 = g.tA == F32, b32 = g.tB == F32;
+  if (a32 && b32) return go_rk<float, float, TM>(g, s);
+  if (a32) return go_rk<float, double, TM>(g, s);
+  if (b32) return go_rk<double, float, TM>(g, s);
+  return go_rk<double, double, TM>(g, s);
+}
+
+}  // namespace
+
+hipError_t launch_gemm_rk(const GemmLaunch& g, hipStream_t s) {
+  return g.math == MATH_F32 ? go_rk_types<float>(g, s) : go_rk_types<double>(g, s);
+}
+
+}  // namespace ht

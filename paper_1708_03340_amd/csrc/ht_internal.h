@@ -63,6 +63,10 @@ struct GemmLaunch {
   bool sb_swap;            //   small operand is B (A streamed along M)
   int sb_grid;             //   workgroups per descriptor
   int sb_wn;               //   16-column MFMA blocks per wave (2: 4 waves, else 8 waves)
+  bool rk;                 // M, N <= 128, long reduction split over workgroups
+  bool rk_sym;             //   B is A^T of the same matrix: upper blocks only
+  int rk_split;            //   workgroups per descriptor along the reduction
+  int rk_kc;               //   k per LDS chunk (16 or 32)
   int ndesc, maxbatch, maxtiles;
   const GemmDesc* descs;   // device pointer
 };
@@ -88,6 +92,7 @@ __device__ __forceinline__ void gatomic_add(float* p, float v) {
 
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t stream);
 hipError_t launch_gemm_sb(const GemmLaunch& g, hipStream_t stream);
+hipError_t launch_gemm_rk(const GemmLaunch& g, hipStream_t stream);
 
 // ---------------------------------------------------------------- small dense kernels
 // Per-node argument block of the small dense kernels (device-resident table).
