@@ -136,8 +136,9 @@ GemmDesc blank_desc() {
 }
 
 // Adds one GEMM launch over `descs` (all sharing types, math, mode, layouts).
+// sym_out: the caller knows that every result C is a symmetric matrix.
 void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode,
-              bool akc, bool bkc, bool acc64 = false, int target_blocks = 4096) {
+              bool akc, bool bkc, bool acc64 = false, int target_blocks = 4096, bool sym_out = false) {
   if (descs.empty()) return;
   Op op;
   op.kind = OP_GEMM;
@@ -181,7 +182,8 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
     }
   }
   // long reductions into a result of at most 128 x 128, split over k
-  // (only the symmetric float64 Gram matrices: for the others the 64 x 64
+  // (only float64 results that are symmetric: a Gram matrix, where B is A^T,
+  // or a result the caller declares symmetric; for the others the 64 x 64
   // tiles are as fast)
   if (mode == GEMM_ATOMIC && !op.g.sb && math == MATH_F64) {
     bool ok = true, sym = tA == tB;
@@ -192,10 +194,14 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
       if (!(d.A == d.B && d.M == d.N && d.sAm == d.sBn && d.sAk == d.sBk && d.sAkb == d.sBkb)) sym = false;
       chunks = std::max<long long>(chunks, (long long)((d.K + 15) / 16) * d.KB);
     }
-    if (ok && sym) {
+    if (ok && (sym || sym_out)) {
+      for (const auto& d : descs)
+        if (d.M != d.N) ok = false;
+    }
+    if (ok && (sym || sym_out)) {
       op.g.rk = true;
-      op.g.rk_sym = sym;
-      op.g.rk_kc = 32;
+      op.g.rk_sym = sym ? 1 : 2;
+      op.g.rk_kc = sym ? 32 : 16;
       const long long want = (1024 + (long long)descs.size() - 1) / (long long)descs.size();
       op.g.rk_split = (int)std::max<long long>(1, std::min(want, (chunks + 15) / 16));
       big = false;
@@ -433,9 +439,9 @@ std::string kernel_name(const Op& op) {
       }
       if (op.g.rk) {
         const std::string tm = op.g.math == MATH_F32 ? "float" : "double";
-        const int kc = op.g.rk_sym && op.g.rk_kc == 32 ? 32 : 16;
+        const int kc = op.g.rk_sym == 1 ? 32 : 16;
         return std::string("gemm_rk_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," + tm + "," +
-               (op.g.rk_sym ? "true" : "false") + "," + std::to_string(kc) + ">";
+               std::to_string(op.g.rk_sym) + "," + std::to_string(kc) + ">";
       }
       if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +
@@ -968,10 +974,11 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
     }
     g_label = "gramian_mode1";
     add_gemm(P, dc, F64, tq, F64, MATH_F64, GEMM_STORE, true, false);
+    // the son Gramians are symmetric because Bhat_t is
     g_label = "gramian_son1";
-    add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true, false, 4096, true);
     g_label = "gramian_son2";
-    add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false);
+    add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false, false, 4096, true);
   }
 }
 

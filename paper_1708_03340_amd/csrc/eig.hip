@@ -37,10 +37,18 @@ __device__ __forceinline__ double rsqrt3(double x) {
   return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-// Sum over a wave of 64 lanes, returned to every lane.
+// Value of v in lane src (src uniform).
+__device__ __forceinline__ double lane_val(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over a wave of 64 lanes, returned to every lane: DPP sums in rows of
+// 16, then the four row sums.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v = row16_sum(v);
+  return ((lane_val(v, 0) + lane_val(v, 16)) + lane_val(v, 32)) + lane_val(v, 48);
 }
 
 enum : int { SWEEP_NONE = 0, SWEEP_ROT = 1, SWEEP_DONE = 2 };
@@ -219,19 +227,24 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
         double r = sqrt(g * g + 1.0);
         g = dg[m] - dg[l] + eo[l] / (g + (g >= 0.0 ? r : -r));
         double sn = 1.0, cs = 1.0, p = 0.0;
-        double d_i1 = dg[m];                 // dg[i+1] for i = m-1
-        double e_i = eo[m - 1], d_i = dg[m - 1];
-        int i = m - 1;
-        for (; i >= l; --i) {
-          // operands of the next rotation (unused after the last one)
-          const double e_n = eo[max(i - 1, l)], d_n = dg[max(i - 1, l)];
+        double d_i1 = dg[m];                 // d[i+1] for i = m-1
+        // rotations i = m-1 .. l.  Whole blocks of eight run as straight-line
+        // code: their operands (e[i], d[i]) are loaded one block ahead and
+        // their results (e[i+1], d[i+1], c_i, s_i) stored after the block, so
+        // neither an LDS access nor a branch sits on the dependent chain.  A
+        // block in which a rotation meets f = g = 0 (a split) is redone
+        // rotation by rotation, as is the tail of fewer than eight.
+        int lo = l;
+        bool split = false;
+        // one rotation with the split test; false on a split at index i
+        auto step = [&](int i, double e_i, double d_i) -> bool {
           const double f = sn * e_i, bb = cs * e_i;
           const double x2 = f * f + g * g;
           if (x2 == 0.0) {  // split: restart on the smaller block
             eo[i + 1] = 0.0;
             dg[i + 1] = d_i1 - p;
-            eo[m] = 0.0;
-            break;
+            lo = i + 1;
+            return false;
           }
           const double ir = rsqrt3(x2);
           eo[i + 1] = x2 * ir;
@@ -245,16 +258,77 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
           rcs[b][i] = cs;
           rss[b][i] = sn;
           d_i1 = d_i;
-          e_i = e_n;
-          d_i = d_n;
+          return true;
+        };
+        double eb[8], db[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = max(m - 1 - u, l);
+          eb[u] = eo[idx];
+          db[u] = dg[idx];
         }
-        if (i < l) {
+        int i0 = m - 1;
+        while (i0 - 7 >= l) {
+          double en[8], dn[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int idx = max(i0 - 8 - u, l);
+            en[u] = eo[idx];
+            dn[u] = dg[idx];
+          }
+          const double sn0 = sn, cs0 = cs, p0 = p, g0 = g, d0 = d_i1;
+          double oe[8], od[8], oc[8], os[8];
+          bool zero = false;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double f = sn * eb[u], bb = cs * eb[u];
+            const double x2 = f * f + g * g;
+            zero = zero || x2 == 0.0;
+            const double ir = rsqrt3(x2);
+            oe[u] = x2 * ir;
+            sn = f * ir;
+            cs = g * ir;
+            g = d_i1 - p;
+            r = (db[u] - g) * sn + 2.0 * cs * bb;
+            p = sn * r;
+            od[u] = g + p;
+            g = cs * r - bb;
+            oc[u] = cs;
+            os[u] = sn;
+            d_i1 = db[u];
+          }
+          if (!zero) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 - u;
+              eo[i + 1] = oe[u];
+              dg[i + 1] = od[u];
+              rcs[b][i] = oc[u];
+              rss[b][i] = os[u];
+            }
+          } else {   // redo the block rotation by rotation
+            sn = sn0; cs = cs0; p = p0; g = g0; d_i1 = d0;
+            for (int u = 0; u < 8 && !split; ++u) split = !step(i0 - u, eb[u], db[u]);
+            if (split) break;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            eb[u] = en[u];
+            db[u] = dn[u];
+          }
+          i0 -= 8;
+        }
+        // the tail: fewer than eight rotations, operands already in eb, db
+        for (int u = 0; u < 8 && !split && i0 - u >= l; ++u) split = !step(i0 - u, eb[u], db[u]);
+        if (split) {
+          eo[m] = 0.0;
+        } else {
           dg[l] = d_i1 - p;
           eo[l] = g;
           eo[m] = 0.0;
         }
         sw_m[b] = m;
-        sw_lo[b] = i + 1;   // rotations m-1 .. lo were formed
+        sw_lo[b] = lo;   // rotations m-1 .. lo were formed
         sw_state[b] = SWEEP_ROT;
         sh_iters += 1;
       }

@@ -11,10 +11,11 @@
 // each operand is contiguous.  Fragments are read as four consecutive k per
 // lane: MFMA q of a 16-deep step then pairs k = 4j + q of A with the same k
 // of B in lane group j, so the four products cover the chunk exactly, with A
-// and B permuted alike.  When B is A^T of the same matrix (a Gram matrix)
-// only the 36 blocks of 16 x 16 on or above the diagonal are formed, each
-// wave taking block rows w and 7-w, and the off-diagonal blocks are added at
-// both places.
+// and B permuted alike.  When the result is symmetric (a Gram matrix, B = A^T
+// of the same matrix, or a son Gramian, which inherits the symmetry of
+// Bhat_t) only the 36 blocks of 16 x 16 on or above the diagonal are formed,
+// each wave taking block rows w and 7-w, and the off-diagonal blocks are
+// added at both places.
 #include "ht_internal.h"
 
 namespace ht {
@@ -41,15 +42,19 @@ template <> struct RkTraits<float> {
   __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
 };
 
-template <typename TA, typename TB, typename TM, bool SYM, int RK_KC>
-__global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __restrict__ descs, int nsplit,
-                                                          int tC, int mode) {
+// MODE 0: full result; 1: Gram matrix (B = A^T, upper blocks); 2: separate B
+// but a symmetric result (upper blocks, mirrored), as for the son Gramians
+template <typename TA, typename TB, typename TM, int MODE, int RK_KC>
+__global__ __launch_bounds__(RK_NT, MODE == 1 ? 2 : 1) void gemm_rk_kernel(const GemmDesc* __restrict__ descs,
+                                                                        int nsplit, int tC, int mode) {
+  constexpr bool SYM = MODE != 0;      // upper blocks only
+  constexpr bool SAMEB = MODE == 1;    // B fragments read from A
   constexpr int LU = RK_KC / 2;   // elements per thread per operand and chunk
   using Tr = RkTraits<TM>;
   using V = typename Tr::V;
   constexpr int LDK = RK_KC + Tr::PAD;
   __shared__ TM As[2][128][LDK];
-  __shared__ TM Bs[SYM ? 1 : 2][SYM ? 1 : 128][LDK];
+  __shared__ TM Bs[SAMEB ? 1 : 2][SAMEB ? 1 : 128][LDK];
 
   const GemmDesc& D = descs[blockIdx.y];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __res
       const TM v = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]);
       ra[u] = v * (TM)(k < K);
     }
-    if (!SYM) {
+    if (!SAMEB) {
       const TB* Bk = Bb + (int64_t)kb * D.sBkb;
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __res
       const int k = a_kc ? (tid & 1) * LU + u : tid / RG;
       As[buf][r][k] = ra[u];
     }
-    if (!SYM) {
+    if (!SAMEB) {
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
         const int n = b_kc ? (tid >> 1) : (tid % RG) * LU + u;
@@ -141,8 +146,8 @@ __global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __res
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           if (SYM && j < wave) continue;   // block columns left of both rows
-          const TM* p = SYM ? &As[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq]
-                            : &Bs[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq];
+          const TM* p = SAMEB ? &As[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq]
+                              : &Bs[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq];
           fb[j][0] = p[0];
           fb[j][1] = p[1];
         }
@@ -198,15 +203,15 @@ __global__ __launch_bounds__(RK_NT, 2) void gemm_rk_kernel(const GemmDesc* __res
 template <typename TA, typename TB, typename TM>
 hipError_t go_rk(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.rk_split, g.ndesc, 1);
-  if (g.rk_sym && g.rk_kc == 32)
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, true, 32>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
-                       g.tC, g.mode);
-  else if (g.rk_sym)
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, true, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
-                       g.tC, g.mode);
+  if (g.rk_sym == 1)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 1, 32>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
+                       g.mode);
+  else if (g.rk_sym == 2)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
+                       g.mode);
   else
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, false, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
-                       g.tC, g.mode);
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 0, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
+                       g.mode);
   return hipGetLastError();
 }
 

@@ -64,9 +64,9 @@ struct GemmLaunch {
   int sb_grid;             //   workgroups per descriptor
   int sb_wn;               //   16-column MFMA blocks per wave (2: 4 waves, else 8 waves)
   bool rk;                 // M, N <= 128, long reduction split over workgroups
-  bool rk_sym;             //   B is A^T of the same matrix: upper blocks only
+  int rk_sym;              //   1: B is A^T of the same matrix; 2: symmetric result (upper blocks only)
   int rk_split;            //   workgroups per descriptor along the reduction
-  int rk_kc;               //   k per LDS chunk (16 or 32)
+  int rk_kc;               //   k per LDS chunk (32 for rk_sym == 1, else 16)
   int ndesc, maxbatch, maxtiles;
   const GemmDesc* descs;   // device pointer
 };
