@@ -1,6 +1,6 @@
-// Cholesky steps of CholeskyQR2, one workgroup per tree node, the node's
-// K x K Gram matrix resident in LDS (K <= 128, row stride K + 1 so that column
-// accesses hit different banks).
+// Cholesky steps of CholeskyQR2, one workgroup of 256 threads per tree node,
+// the node's K x K Gram matrix in LDS (K <= 128, padded to whole 16 x 16
+// blocks with an identity).
 //
 // Section 3.4 asks for a reduced QR of every leaf frame and of M_{2,3}(B_t);
 // CholeskyQR2 gets R from two Gram matrices: G = W^T W = R1^T R1, then
@@ -9,184 +9,211 @@
 //    float32 may be indefinite); the second sweep repairs R;
 //  * sweep 2 drops the rows whose pivot vanishes (rank-deficient frames such
 //    as those of the sum A + A) and flags them.
-// The factor and the inverse are both formed with the matrix held in
-// registers across all steps, so a step costs a few LDS reads and at most one
-// barrier instead of a round trip of the trailing matrix through LDS.
+//
+// Right-looking blocked factorisation, blocks of 16.  For each block column
+// p: wave 0 factors the diagonal block in LDS (one pivot at a time) and
+// inverts its factor; the block row R_pq = R_pp^{-T} A_pq and the symmetric
+// trailing update A_qr -= R_pq^T R_pr are float64 MFMA 16x16x4 products
+// spread over the four waves.  R^{-1} is then formed by blocked back
+// substitution, X_pq = -X_pp sum_{k=p+1..q} R_pk X_kq, also on MFMA.  A
+// dropped row is a zero row of R and a unit row of the matrix inverted.
 #include "dense_util.h"
 
 namespace ht {
 namespace {
 
 constexpr int NT = DNT;
+constexpr int LDL = KMAX + 1;   // LDS row stride of the matrix
+constexpr int LDD = 17;         // LDS row stride of a 16 x 16 block inverse
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// Thread (ty, tx) = (tid / 16, tid % 16) owns the entries (ty + 16i, tx + 16q)
-// of the upper block triangle q >= i of a KMAX x KMAX matrix: 36 values kept
-// in registers for the whole factorisation.
-//
-// Cholesky G = R^T R, right-looking in LDL^T form (rows stay unscaled and are
-// divided by sqrt(pivot) at the end).  Step j reads the pivot row j from a
-// double-buffered row in LDS, applies the rank-1 update to the whole register
-// tile and the owners of row j+1 publish it (to the row buffer and to L): one
-// barrier per step.  Entries of rows or columns that are already eliminated,
-// or that lie past K or below the diagonal, receive meaningless updates; they
-// never feed an entry that is still live and are never read.
-// sweep 1: a pivot <= tol is replaced by tol; sweep 2: its row is dropped
-// (dropped[j] = 1, zero row).  Returns true if a row was dropped.  On return
-// L holds the scaled R (zero below the diagonal and on dropped rows).
-__device__ bool chol_regs(double* L, int K, int ld, double tol, int sweep, int* dropped, double* piv,
-                          double (*rowbuf)[KMAX]) {
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  __shared__ int any;
-  double v[8][8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int q = i; q < 8; ++q) {
-      const int a = ty + 16 * i, c = tx + 16 * q;
-      v[i][q] = (a < K && c < K) ? L[a * ld + c] : 0.0;
-    }
-  if (tid == 0) any = 0;
-  if (ty == 0) {   // publish row 0
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rowbuf[0][tx + 16 * q] = v[0][q];
-  }
-  for (int j = 0; j < K; ++j) {
-    __syncthreads();
-    const double* rb = rowbuf[j & 1];
-    double pj = rb[j];
-    bool drop = false;
-    if (!(pj > tol)) {
-      if (sweep == 1) pj = tol; else drop = true;
-    }
-    if (tid == 0) { piv[j] = drop ? 0.0 : pj; dropped[j] = drop ? 1 : 0; if (drop) any = 1; }
-    if (!drop) {
-      const double inv = rcp_nr(pj);
-      double lr[8], lc[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        lr[i] = rb[ty + 16 * i] * inv;
-        lc[i] = rb[tx + 16 * i];
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int q = i; q < 8; ++q) v[i][q] -= lr[i] * lc[q];
-    }
-    // publish row j+1 (after this step's update) into the other buffer and L
-    const int jn = j + 1;
-    if (jn < K && ty == (jn & 15)) {
-      const int ib = jn >> 4;
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i == ib) {
-#pragma unroll
-          for (int q = i; q < 8; ++q) {
-            const int c = tx + 16 * q;
-            rowbuf[jn & 1][c] = v[i][q];
-            if (c < K) L[jn * ld + c] = v[i][q];
-          }
-        }
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int a = idx / K, c = idx % K;
-    double& x = L[a * ld + c];
-    if (c < a || dropped[a]) x = 0.0;
-    else {
-      const double r = sqrt(piv[a]);
-      x = c == a ? r : x / r;
-    }
-  }
-  __syncthreads();
-  return any != 0;
-}
-
-// X = R^{-1} for the upper-triangular R in L (rows marked in `dropped` get a
-// unit diagonal), column by column: X[i][j] = -(sum_k X[i][k] R[k][j]) / R[j][j]
-// for i < j.  Thread (g, l) = (tid / 16, tid % 16) keeps X[g + 16m][l + 16p],
-// p >= m, in registers; entries not yet computed are zero, so the dot product
-// over its columns needs no masks.  The 16 lanes of a row group (one DPP row)
-// sum with DPP moves and the owner of column j stores the result: no
-// barriers.  X is written to Xout (K x K, row-major).
-__device__ void trinv_regs(const double* L, int K, int ld, const int* dropped, double* Xout) {
-  const int tid = threadIdx.x;
-  const int g = tid >> 4, l = tid & 15;
-  double x[8][8];
-#pragma unroll
-  for (int m = 0; m < 8; ++m)
-#pragma unroll
-    for (int p = m; p < 8; ++p) x[m][p] = 0.0;
-  for (int j = 0; j < K; ++j) {
-    const int jb = j >> 4;
-    const double ajj = rcp_nr(dropped[j] ? 1.0 : L[j * ld + j]);
-    double r[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) r[p] = L[min(l + 16 * p, K - 1) * ld + j];
-    const bool owner = l == (j & 15);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      if (m <= jb) {     // rows g + 16m < j exist only in blocks m <= j / 16
-        double s = 0.0;
-#pragma unroll
-        for (int p = m; p < 8; ++p)
-          if (p <= jb) s += x[m][p] * r[p];
-        s = row16_sum(s);
-        const int i = g + 16 * m;
-        const double xij = i < j ? -s * ajj : (i == j ? ajj : 0.0);
-#pragma unroll
-        for (int p = m; p < 8; ++p)
-          if (p == jb && owner) x[m][p] = xij;
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < 8; ++m)
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int i = g + 16 * m, k = l + 16 * p;
-      if (i < K && k < K) gst(&Xout[i * K + k], p >= m ? x[m][p] : 0.0);
-    }
+__device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // sweep 1: G -> R1, Ri1 = R1^{-1}.  sweep 2: G2 -> R2 (rows of vanishing
 // pivots dropped), R2i = inverse of R2 with unit diagonal on dropped rows.
 __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ args, int sweep,
                                                   GlobalState* st) {
-  __shared__ double L[KMAX * (KMAX + 1)];
-  __shared__ double rowbuf[2][KMAX];
+  __shared__ double L[KMAX * LDL];            // A, then R (upper blocks) and X^T (lower blocks)
+  __shared__ double Xd[KMAX / 16][16 * LDD];  // inverses of the diagonal blocks of R
   __shared__ double red[NT / 64];
   __shared__ double piv[KMAX];
   __shared__ int dropped[KMAX];
+  __shared__ int any;
   const SmallArgs& a = args[blockIdx.x];
-  const int K = a.K, ld = K + 1;
-  const int tid = threadIdx.x;
+  const int K = a.K;
+  const int NB = (K + 15) >> 4, Kp = NB * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
   const double* Gin = sweep == 1 ? a.G : a.G2;
   bool bad = false;
-  for (int i = tid; i < K * K; i += NT) {
-    const double v = gld(&Gin[i]);
-    if (!isfinite(v)) bad = true;
-    L[(i / K) * ld + i % K] = v;
+  for (int i = tid; i < Kp * Kp; i += NT) {
+    const int r = i / Kp, c = i % Kp;
+    double v = r == c ? 1.0 : 0.0;   // identity on the padding
+    if (r < K && c < K) {
+      v = gld(&Gin[r * K + c]);
+      if (!isfinite(v)) bad = true;
+    }
+    L[r * LDL + c] = v;
   }
-  for (int i = tid; i < K; i += NT) dropped[i] = 0;
+  for (int i = tid; i < KMAX; i += NT) dropped[i] = 0;
+  if (tid == 0) any = 0;
   __syncthreads();
   double md = 0.0;
   for (int i = tid; i < K; i += NT) {
-    const double v = L[i * ld + i];
+    const double v = L[i * LDL + i];
     if (isfinite(v)) md = fmax(md, v);
   }
   const double maxd = wg_max(md, red);
   const double badany = wg_max(bad ? 1.0 : 0.0, red);
   if (badany > 0.0 && tid == 0) atomicOr(&st->flags, 2u);
   const double tol = maxd > 0.0 ? a.tol_rel * maxd : 1.0;
-  const bool ev = chol_regs(L, K, ld, tol, sweep, dropped, piv, rowbuf);
+
+  for (int p = 0; p < NB; ++p) {
+    double* D = &L[16 * p * LDL + 16 * p];
+    // ---- diagonal block: unblocked Cholesky by wave 0 (lane: row l16,
+    // columns 4 l4 .. 4 l4 + 3), then the inverse of its factor
+    if (wave == 0) {
+      for (int j = 0; j < 16; ++j) {
+        const int g = 16 * p + j;
+        double pj = D[j * LDL + j];
+        bool drop = false;
+        if (g >= K) pj = 1.0;   // padding
+        else if (!(pj > tol)) {
+          if (sweep == 1) pj = tol; else drop = true;
+        }
+        if (lane == 0) {
+          piv[g] = drop ? 0.0 : pj;
+          dropped[g] = drop ? 1 : 0;
+          if (drop) any = 1;
+        }
+        if (!drop) {
+          const double mult = D[l16 * LDL + j] * rcp_nr(pj);
+          double upd[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) upd[u] = D[l16 * LDL + 4 * l4 + u] - mult * D[j * LDL + 4 * l4 + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = 4 * l4 + u;
+            if (l16 > j && c > j) D[l16 * LDL + c] = upd[u];
+          }
+        }
+      }
+      // scale the rows: R_pp (zero below the diagonal and on dropped rows)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = l16, c = 4 * l4 + u, g = 16 * p + r;
+        double v = 0.0;
+        if (!dropped[g] && c >= r) {
+          const double s = sqrt(piv[g]);
+          v = c == r ? s : D[r * LDL + c] / s;
+        }
+        D[r * LDL + c] = v;
+      }
+      // X_pp = R_pp^{-1} (unit diagonal on dropped rows), lanes 0..15 one column each
+      if (lane < 16) {
+        const int c = lane;
+        double x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          if (i > c) {
+            x[i] = 0.0;
+          } else {
+            const bool di = dropped[16 * p + i] != 0;
+            double s = i == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = i + 1; k < 16; ++k)
+              if (k <= c) s -= D[i * LDL + k] * x[k];
+            x[i] = s * rcp_nr(di ? 1.0 : D[i * LDL + i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Xd[p][i * LDD + c] = x[i];
+      }
+    }
+    __syncthreads();
+    // ---- block row: R_pq = X_pp^T A_pq, dropped rows zeroed
+    for (int q = p + 1 + wave; q < NB; q += 4) {
+      doublex4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + l4;
+        acc = mfma(Xd[p][k * LDD + l16], L[(16 * p + k) * LDL + 16 * q + l16], acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + l4;
+        L[(16 * p + r) * LDL + 16 * q + l16] = dropped[16 * p + r] ? 0.0 : acc[v];
+      }
+    }
+    __syncthreads();
+    // ---- trailing update of the upper blocks: A_qr -= R_pq^T R_pr, p < q <= r
+    {
+      const int nt = NB - 1 - p;
+      int idx = 0;
+      for (int q = p + 1; q < NB; ++q)
+        for (int r = q; r < NB; ++r, ++idx) {
+          if ((idx & 3) != wave) continue;
+          doublex4 acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = L[(16 * q + 4 * v + l4) * LDL + 16 * r + l16];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = 16 * p + 4 * s + l4;
+            acc = mfma(-L[k * LDL + 16 * q + l16], L[k * LDL + 16 * r + l16], acc);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) L[(16 * q + 4 * v + l4) * LDL + 16 * r + l16] = acc[v];
+        }
+      (void)nt;
+    }
+    __syncthreads();
+  }
+
+  // ---- R out (upper blocks of L; zero below the diagonal)
   double* Rout = sweep == 1 ? a.R1 : a.R2;
   double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
-  for (int i = tid; i < K * K; i += NT) gst(&Rout[i], L[(i / K) * ld + i % K]);
-  trinv_regs(L, K, ld, dropped, Riout);
-  if (sweep == 2 && ev && tid == 0) atomicOr(&st->flags, 1u);
+  for (int i = tid; i < K * K; i += NT) {
+    const int r = i / K, c = i % K;
+    gst(&Rout[i], c >= r ? L[r * LDL + c] : 0.0);
+  }
+  __syncthreads();   // the lower blocks of L are overwritten below
+
+  // ---- X = R^{-1} by blocked back substitution; X_pq (p < q) is kept
+  // transposed in the lower block (q, p) of L, X_pp in Xd[p]
+  for (int p = NB - 2; p >= 0; --p) {
+    for (int q = p + 1 + wave; q < NB; q += 4) {
+      // S = sum_{k=p+1..q} R_pk X_kq
+      doublex4 sacc = {0, 0, 0, 0};
+      for (int k = p + 1; k <= q; ++k) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kk = 4 * s + l4;
+          const double ra = L[(16 * p + l16) * LDL + 16 * k + kk];
+          const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
+          sacc = mfma(ra, xb, sacc);
+        }
+      }
+      // X_pq = -X_pp S: the accumulator layout of S is the B operand layout
+      doublex4 xacc = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xacc = mfma(-Xd[p][l16 * LDD + 4 * s + l4], sacc[s], xacc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) L[(16 * q + l16) * LDL + 16 * p + 4 * v + l4] = xacc[v];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < K * K; i += NT) {
+    const int r = i / K, c = i % K;
+    const int pr = r >> 4, pc = c >> 4;
+    double v = 0.0;
+    if (pr == pc) v = Xd[pr][(r & 15) * LDD + (c & 15)];
+    else if (pr < pc) v = L[c * LDL + r];
+    gst(&Riout[i], v);
+  }
+  if (sweep == 2 && any && tid == 0) atomicOr(&st->flags, 1u);
 }
 
 // R (= R2 R1, formed by a GEMM) is divided by 2^e, e the binary exponent of
