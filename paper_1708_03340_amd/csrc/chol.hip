@@ -49,14 +49,27 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const int l16 = lane & 15, l4 = lane >> 4;
   const double* Gin = sweep == 1 ? a.G : a.G2;
   bool bad = false;
-  for (int i = tid; i < Kp * Kp; i += NT) {
-    const int r = i / Kp, c = i % Kp;
-    double v = r == c ? 1.0 : 0.0;   // identity on the padding
-    if (r < K && c < K) {
-      v = gld(&Gin[r * K + c]);
-      if (!isfinite(v)) bad = true;
-    }
-    L[r * LDL + c] = v;
+  // wave w loads rows w, w + 4, ...; lane c columns c and c + 64; eight rows
+  // in flight per wave
+  for (int r0 = wave; r0 < Kp; r0 += 32) {
+    double v[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + 4 * u, c = lane + 64 * h;
+        v[u][h] = (r < K && c < K) ? gld(&Gin[r * K + c]) : (r == c ? 1.0 : 0.0);   // identity on the padding
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + 4 * u, c = lane + 64 * h;
+        if (r < Kp && c < Kp) {
+          if (!isfinite(v[u][h])) bad = true;
+          L[r * LDL + c] = v[u][h];
+        }
+      }
   }
   for (int i = tid; i < KMAX; i += NT) dropped[i] = 0;
   if (tid == 0) any = 0;
