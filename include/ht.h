@@ -185,6 +185,30 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
                       int64_t* out_log2_scale, uint32_t* flags, double* out_sigma,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- batched truncation
+ * Truncates `count` independent lazy sums in one pass: problem c is the sum of
+ * X[o_c .. o_c + n_in[c]) (o_c = n_in[0] + .. + n_in[c-1]) with coefficients
+ * coef[o_c ..] (coef may be NULL: all 1), options opts[c] and result out[c],
+ * each exactly as for ht_truncate (Section 3.3, the same algorithm and the
+ * same precision policy per problem).  Problems may differ in d, n, ranks,
+ * dtypes, rank mode and precision.  The launches of the problems are merged
+ * step by step (all leaf Grams of the batch in one launch, all Cholesky
+ * factorisations of one level in one launch, ...), so the number of launches
+ * does not grow with `count`.
+ * out_ranks: host array [count] of DEVICE int32[2d_c-1] (the array or any
+ * entry may be NULL).  out_log2_scale: DEVICE int64[count], required.  flags:
+ * DEVICE uint32[count] or NULL.  out_sigma: host array [count] of DEVICE
+ * float64 [2d_c-1][128] (the array or any entry may be NULL).  The results of
+ * different problems must not overlap.  Workspace: the sum over the problems
+ * of their ht_truncate_workspace() sizes, each rounded up to 256 bytes.
+ * Errors: as ht_truncate; the message names the problem. */
+ht_status ht_truncate_batched_workspace(ht_context* ctx, int32_t count, const ht_desc* X,
+                                        const int32_t* n_in, const ht_trunc_opts* opts, size_t* bytes);
+ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
+                              const double* coef, const ht_trunc_opts* opts, const ht_desc* out,
+                              int32_t* const* out_ranks, int64_t* out_log2_scale, uint32_t* flags,
+                              double* const* out_sigma, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- entries
  * A[i_1..i_d] for m multi-indices (Section 3.1): leaves pick row i_mu, inner
  * nodes apply eq. (transfermult), the root the root formula; evaluated level

@@ -17,6 +17,9 @@
 extern "C" {
 #endif
 ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts);
+/* also returns the number of launches of the merged plan (n_launches may be NULL) */
+ht_status ht_debug_validate_truncate_batched(int32_t count, const ht_desc* X, const int32_t* n_in,
+                                             const ht_trunc_opts* opts, int32_t* n_launches);
 ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision);
 ht_status ht_debug_validate_gramians(const ht_desc* X);
 ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m);

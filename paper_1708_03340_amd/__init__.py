@@ -26,7 +26,8 @@ KMAX = 128
 EXPORTS = [
     "ht_create_context", "ht_destroy_context", "ht_status_string", "ht_last_error", "ht_version",
     "ht_tree", "ht_add", "ht_orthogonalize_workspace", "ht_orthogonalize", "ht_gramians_workspace",
-    "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_entries_workspace", "ht_entries",
+    "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_truncate_batched_workspace",
+    "ht_truncate_batched", "ht_entries_workspace", "ht_entries",
     "ht_profile_enable", "ht_profile_read", "ht_profile_reset",
 ]
 
@@ -99,6 +100,9 @@ def lib(path: Optional[str] = None):
     L.ht_truncate_workspace.argtypes = [VP, P(HtDesc), I32, P(HtTruncOpts), P(ctypes.c_size_t)]
     L.ht_truncate.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, P(HtTruncOpts), P(HtDesc), VP, VP, VP,
                               VP, VP, ctypes.c_size_t, VP]
+    L.ht_truncate_batched_workspace.argtypes = [VP, I32, P(HtDesc), P(I32), P(HtTruncOpts), P(ctypes.c_size_t)]
+    L.ht_truncate_batched.argtypes = [VP, I32, P(HtDesc), P(I32), P(ctypes.c_double), P(HtTruncOpts), P(HtDesc),
+                                      P(VP), VP, VP, P(VP), VP, ctypes.c_size_t, VP]
     L.ht_entries_workspace.argtypes = [VP, P(HtDesc), I64, P(ctypes.c_size_t)]
     L.ht_entries.argtypes = [VP, P(HtDesc), I64, VP, VP, VP, ctypes.c_size_t, VP]
     L.ht_profile_enable.argtypes = [VP, I32]
@@ -442,6 +446,78 @@ def ht_truncate(Xs, coef=None, **kw) -> TruncResult:
     if isinstance(Xs, DeviceHT):
         Xs = [Xs]
     return Truncator(Xs, coef, **kw)()
+
+
+class BatchTruncator:
+    """Reusable ht_truncate_batched call over independent problems.
+
+    problems: list of dicts with keys ``Xs`` (summands, a list of DeviceHT),
+    optional ``coef`` and the Truncator keywords ``mode``, ``ranks``, ``eps``,
+    ``relative``, ``max_rank``, ``precision``, ``out_frame_dtype``,
+    ``out_transfer_dtype``.  __call__ enqueues every truncation on the current
+    stream and returns one TruncResult per problem."""
+
+    def __init__(self, problems, *, want_sigma=False, ctx=None):
+        import torch
+        self.ctx = ctx or ht_create_context()
+        self.count = len(problems)
+        if self.count < 1:
+            raise HTError("no problems")
+        allx, coef, n_in = [], [], []
+        self.opts = (HtTruncOpts * self.count)()
+        self._rks, self.outs = [], []
+        for c, pb in enumerate(problems):
+            Xs = list(pb["Xs"])
+            d = Xs[0].d
+            nn = 2 * d - 1
+            allx += Xs
+            n_in.append(len(Xs))
+            coef += [1.0] * len(Xs) if pb.get("coef") is None else [float(v) for v in pb["coef"]]
+            mode = pb.get("mode", HT_RANK_FIXED)
+            rk = list(pb["ranks"]) if pb.get("ranks") is not None else [1] * nn
+            rka = (ctypes.c_int32 * nn)(*rk)
+            self._rks.append(rka)
+            prec = pb.get("precision", HT_PREC_MIXED)
+            max_rank = int(pb.get("max_rank", 0))
+            self.opts[c] = HtTruncOpts(mode, ctypes.cast(rka, ctypes.POINTER(ctypes.c_int32)),
+                                       float(pb.get("eps", 0.0)), 1 if pb.get("relative", True) else 0, max_rank,
+                                       prec)
+            fdt = pb.get("out_frame_dtype") or (torch.float32 if prec == HT_PREC_MIXED else torch.float64)
+            tdt = pb.get("out_transfer_dtype") or fdt
+            self.outs.append(DeviceHT.empty(d, Xs[0].n, out_ranks_for(Xs, mode, rk, max_rank), fdt, tdt))
+        self.Xs = allx
+        self.xdescs, self._keep = _descs(allx)
+        self.n_in = (ctypes.c_int32 * self.count)(*n_in)
+        self.coef = (ctypes.c_double * len(coef))(*coef)
+        self.odescs, self._okeep = _descs(self.outs)
+        need = ctypes.c_size_t(0)
+        _check(lib().ht_truncate_batched_workspace(self.ctx.h, self.count, self.xdescs, self.n_in, self.opts,
+                                                   ctypes.byref(need)))
+        self.ws = _ws(need.value)
+        self.ws_bytes = need.value
+        self.ranks = [torch.zeros(2 * o.d - 1, dtype=torch.int32, device="cuda") for o in self.outs]
+        self.scale = torch.zeros(self.count, dtype=torch.int64, device="cuda")
+        self.flags = torch.zeros(self.count, dtype=torch.int32, device="cuda")
+        self.sigma = ([torch.zeros((2 * o.d - 1, KMAX), dtype=torch.float64, device="cuda") for o in self.outs]
+                      if want_sigma else None)
+        self._rp = (ctypes.c_void_p * self.count)(*[r.data_ptr() for r in self.ranks])
+        self._sp = (ctypes.c_void_p * self.count)(*[s.data_ptr() for s in self.sigma]) if want_sigma else None
+
+    def __call__(self, stream=None):
+        _check(lib().ht_truncate_batched(self.ctx.h, self.count, self.xdescs, self.n_in, self.coef, self.opts,
+                                         self.odescs, self._rp, _ptr(self.scale), _ptr(self.flags), self._sp,
+                                         _ptr(self.ws), self.ws_bytes, _stream_ptr(stream)))
+        res = []
+        for c, o in enumerate(self.outs):
+            o.log2_scale = self.scale[c:c + 1]
+            res.append(TruncResult(o, self.ranks[c], self.scale[c:c + 1], self.flags[c:c + 1],
+                                   self.sigma[c] if self.sigma is not None else None))
+        return res
+
+
+def ht_truncate_batched(problems, **kw):
+    """Truncate many independent sums in one pass (list of TruncResult)."""
+    return BatchTruncator(problems, **kw)()
 
 
 def ht_entries(X: DeviceHT, idx, ctx=None, stream=None):

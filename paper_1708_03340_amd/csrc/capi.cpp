@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <list>
+#include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -76,8 +78,10 @@ enum OpKind : int {
 struct Op {
   int kind = 0;
   GemmLaunch g{};            // OP_GEMM (descs = table offset until bound)
-  size_t toff = 0;           // table offset of descriptors / small args
+  size_t toff = 0;           // table offset of descriptors / records
   int count = 0;
+  size_t toff2 = 0;          // OP_RANK: table offset of the per-tensor StateRecs
+  int count2 = 0;
   void* p0 = nullptr;        // generic pointers
   void* p1 = nullptr;
   void* p2 = nullptr;
@@ -85,10 +89,13 @@ struct Op {
   long long scale0 = 0;
   int i0 = 0, i1 = 0, i2 = 0, i3 = 0, i4 = 0, i5 = 0;
   double f0 = 0.0;
-  int64_t c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // OP_COPY sizes and strides
+  int64_t c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // OP_COPY: c[0] = largest record; entries: row count
   const char* label = "";    // step of the method this launch belongs to
   double flops = 0.0;        // algorithmic flops of the launch
   double bytes_alg = 0.0;    // compulsory bytes moved by the launch
+  int tblocks = 4096;        // OP_GEMM: target workgroups of a split reduction
+  bool sym_out = false;      // OP_GEMM: every result is symmetric
+  bool acc64_req = false;    // OP_GEMM: float64 accumulation across k-slabs was asked for
 };
 
 // Label given to the launches added next (one per step of the method).
@@ -136,12 +143,16 @@ GemmDesc blank_desc() {
 }
 
 // Adds one GEMM launch over `descs` (all sharing types, math, mode, layouts).
+// The launch of a GEMM over `descs` (all sharing types, math, mode and
+// layouts): kernel choice, tiling and split; the descriptors are not stored.
 // sym_out: the caller knows that every result C is a symmetric matrix.
-void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode,
-              bool akc, bool bkc, bool acc64 = false, int target_blocks = 4096, bool sym_out = false) {
-  if (descs.empty()) return;
+Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode, bool akc, bool bkc,
+           bool acc64, int target_blocks, bool sym_out) {
   Op op;
   op.kind = OP_GEMM;
+  op.tblocks = target_blocks;
+  op.sym_out = sym_out;
+  op.acc64_req = acc64;
   // large float64 problems use 128 x 128 tiles
   // (only when there are enough output tiles to fill the chip without
   // splitting the reduction; split-K problems keep 64 x 64 tiles)
@@ -242,8 +253,15 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
     op.bytes_alg += nb * ((double)d.M * kt * (tA == F32 ? 4 : 8) + kt * d.N * (tB == F32 ? 4 : 8) +
                           (double)d.M * d.N * (tC == F32 ? 4 : 8));
   }
-  op.toff = put(P, descs);
   op.count = (int)descs.size();
+  return op;
+}
+
+void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math, int mode,
+              bool akc, bool bkc, bool acc64 = false, int target_blocks = 4096, bool sym_out = false) {
+  if (descs.empty()) return;
+  Op op = gemm_op(descs, tA, tB, tC, math, mode, akc, bkc, acc64, target_blocks, sym_out);
+  op.toff = put(P, descs);
   P.ops.push_back(op);
 }
 
@@ -258,25 +276,244 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
   P.ops.push_back(op);
 }
 
+void add_fills(Plan& P, const std::vector<FillRec>& r) {
+  size_t mx = 0;
+  for (const auto& f : r) mx = std::max(mx, f.bytes);
+  if (!mx) return;
+  Op op; op.kind = OP_FILL; op.toff = put(P, r); op.count = (int)r.size(); op.bytes = mx; op.label = g_label;
+  for (const auto& f : r) op.bytes_alg += (double)f.bytes;
+  P.ops.push_back(op);
+}
+
 void add_fill(Plan& P, void* ptr, size_t bytes) {
   if (!bytes) return;
-  Op op; op.kind = OP_FILL; op.p0 = ptr; op.bytes = bytes; op.label = g_label;
+  add_fills(P, {FillRec{ptr, bytes}});
+}
+
+void add_copies(Plan& P, const std::vector<CopyRec>& r) {
+  int64_t mx = 0;
+  for (const auto& c : r) mx = std::max<int64_t>(mx, c.n0 * c.n1 * c.n2);
+  if (mx <= 0) return;
+  Op op; op.kind = OP_COPY; op.toff = put(P, r); op.count = (int)r.size(); op.c[0] = mx; op.label = g_label;
+  for (const auto& c : r) op.bytes_alg += (double)(c.n0 * c.n1 * c.n2) * (esize(c.tsrc) + esize(c.tdst));
   P.ops.push_back(op);
 }
 
 void add_copy3(Plan& P, const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
                int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2, double alpha) {
-  Op op; op.kind = OP_COPY; op.p0 = const_cast<void*>(src); op.p1 = dst; op.i0 = tsrc; op.i1 = tdst;
-  op.label = g_label;
-  const int64_t v[9] = {n0, n1, n2, s0, s1, s2, d0, d1, d2};
-  for (int i = 0; i < 9; ++i) op.c[i] = v[i];
-  op.f0 = alpha;
-  P.ops.push_back(op);
+  CopyRec c;
+  std::memset(&c, 0, sizeof(c));
+  c.src = src; c.dst = dst; c.tsrc = tsrc; c.tdst = tdst;
+  c.n0 = n0; c.n1 = n1; c.n2 = n2; c.s0 = s0; c.s1 = s1; c.s2 = s2; c.d0 = d0; c.d1 = d1; c.d2 = d2;
+  c.alpha = alpha;
+  add_copies(P, {c});
 }
 
 void add_copy(Plan& P, const void* src, int tsrc, void* dst, int tdst, int64_t rows, int64_t cols,
               int64_t srs, int64_t scs, int64_t drs, int64_t dcs, double alpha) {
   add_copy3(P, src, tsrc, dst, tdst, 1, rows, cols, 0, srs, scs, 0, drs, dcs, alpha);
+}
+
+StateRec blank_state(GlobalState* st) {
+  StateRec r;
+  std::memset(&r, 0, sizeof(r));
+  r.st = st;
+  return r;
+}
+
+// One state op (OP_SETSTATE, OP_ROOTNORM, OP_WRITESCALE) over per-tensor records.
+void add_state(Plan& P, int kind, const std::vector<StateRec>& r) {
+  if (r.empty()) return;
+  Op op; op.kind = kind; op.toff = put(P, r); op.count = (int)r.size(); op.label = g_label;
+  P.ops.push_back(op);
+}
+
+// The launches of one GEMM step over many problems (a batch of tensors): the
+// descriptors are grouped by the kernel that suits each one alone (small
+// operand in LDS with the other streamed, split-K symmetric, tiled), and each
+// group is cut so that its grid stays within the launch limits (the tiled
+// kernels put descriptors x batch on the third grid axis).
+void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& proto) {
+  const GemmLaunch& q = proto.g;
+  auto decide = [&](const std::vector<GemmDesc>& v) {
+    return gemm_op(v, q.tA, q.tB, q.tC, q.math, q.mode, q.a_kcontig, q.b_kcontig, proto.acc64_req,
+                   proto.tblocks, proto.sym_out);
+  };
+  std::vector<std::vector<GemmDesc>> cls(5);
+  for (const auto& d : descs) {
+    const Op one = decide({d});
+    const int c = one.g.sb ? (one.g.sb_swap ? 1 : 0) : (one.g.rk ? 1 + one.g.rk_sym : 4);
+    cls[c].push_back(d);
+  }
+  constexpr long long kGridMax = 65535;
+  for (const auto& v : cls) {
+    size_t i = 0;
+    while (i < v.size()) {
+      std::vector<GemmDesc> chunk;
+      long long mb = 1;
+      while (i < v.size()) {
+        const long long nb = std::max<long long>(mb, v[i].nbatch);
+        if (!chunk.empty() && (long long)(chunk.size() + 1) * nb > kGridMax) break;
+        mb = nb;
+        chunk.push_back(v[i++]);
+      }
+      Op op = decide(chunk);
+      op.label = proto.label;
+      op.toff = put(P, chunk);
+      P.ops.push_back(op);
+    }
+  }
+}
+
+// Interleaves the launch plans of independent problems (the tensors of a
+// batch) into one plan whose launches each serve every problem at the same
+// step.  A step is identified by (kind, label, occurrence of that pair in its
+// plan).  The plans are consumed from their heads: at each turn the step taken
+// is one that no plan still holds behind its head, so the launches of one step
+// are merged whole; each plan's own order is kept, which is all its
+// correctness needs (the problems share no written memory).
+ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
+  const int n = (int)plans.size();
+  std::vector<std::vector<std::string>> key(n);
+  std::vector<std::map<std::string, int>> pos(n);
+  for (int p = 0; p < n; ++p) {
+    std::map<std::string, int> occ;
+    for (size_t i = 0; i < plans[p].ops.size(); ++i) {
+      const Op& op = plans[p].ops[i];
+      const std::string base = std::to_string(op.kind) + "|" + (op.label ? op.label : "");
+      const std::string k = base + "|" + std::to_string(occ[base]++);
+      key[p].push_back(k);
+      pos[p][k] = (int)i;
+    }
+  }
+  std::vector<int> head(n, 0);
+  auto done = [&](int p) { return head[p] >= (int)key[p].size(); };
+  while (true) {
+    int first = -1;
+    for (int p = 0; p < n && first < 0; ++p)
+      if (!done(p)) first = p;
+    if (first < 0) break;
+    std::string chosen;
+    std::set<std::string> tried;
+    for (int p = first; p < n && chosen.empty(); ++p) {
+      if (done(p)) continue;
+      const std::string& k = key[p][head[p]];
+      if (!tried.insert(k).second) continue;
+      bool ok = true;
+      for (int q = 0; q < n && ok; ++q) {
+        if (done(q)) continue;
+        auto it = pos[q].find(k);
+        if (it != pos[q].end() && it->second != head[q]) ok = false;
+      }
+      if (ok) chosen = k;
+    }
+    if (chosen.empty()) chosen = key[first][head[first]];
+    std::vector<std::pair<int, const Op*>> grp;
+    for (int p = 0; p < n; ++p)
+      if (!done(p) && key[p][head[p]] == chosen) {
+        grp.push_back({p, &plans[p].ops[head[p]]});
+        ++head[p];
+      }
+    const Op& o0 = *grp[0].second;
+    auto tab = [&](int p, size_t off) { return plans[p].table.data() + off; };
+    switch (o0.kind) {
+      case OP_GEMM: {
+        // one merged step per set of launch parameters
+        std::vector<bool> used(grp.size(), false);
+        for (size_t i = 0; i < grp.size(); ++i) {
+          if (used[i]) continue;
+          const Op& a = *grp[i].second;
+          std::vector<GemmDesc> ds;
+          for (size_t j = i; j < grp.size(); ++j) {
+            const Op& b = *grp[j].second;
+            if (used[j] || b.g.tA != a.g.tA || b.g.tB != a.g.tB || b.g.tC != a.g.tC || b.g.math != a.g.math ||
+                b.g.mode != a.g.mode || b.g.a_kcontig != a.g.a_kcontig || b.g.b_kcontig != a.g.b_kcontig ||
+                b.acc64_req != a.acc64_req || b.tblocks != a.tblocks || b.sym_out != a.sym_out)
+              continue;
+            used[j] = true;
+            const GemmDesc* src = reinterpret_cast<const GemmDesc*>(tab(grp[j].first, b.toff));
+            ds.insert(ds.end(), src, src + b.count);
+          }
+          add_gemm_grouped(M, ds, a);
+        }
+        break;
+      }
+      case OP_CHOL1: case OP_CHOL2: case OP_FINISHR: case OP_EIG: case OP_PROJPREP: case OP_RANK: {
+        std::vector<SmallArgs> sa;
+        std::vector<StateRec> sr;
+        Op op = o0;
+        op.flops = op.bytes_alg = 0.0;
+        for (const auto& pr : grp) {
+          const Op& b = *pr.second;
+          const SmallArgs* src = reinterpret_cast<const SmallArgs*>(tab(pr.first, b.toff));
+          const int a0 = (int)sa.size();
+          for (int j = 0; j < b.count; ++j) {
+            SmallArgs a = src[j];
+            if (!a.st) a.st = reinterpret_cast<GlobalState*>(b.p0);
+            if (!a.st) return fail(HT_EUNSUPPORTED, "batched plan: node arguments without their tensor state");
+            sa.push_back(a);
+          }
+          if (b.kind == OP_RANK) {
+            const StateRec* rs = reinterpret_cast<const StateRec*>(tab(pr.first, b.toff2));
+            for (int j = 0; j < b.count2; ++j) {
+              StateRec r = rs[j];
+              r.a0 += a0;
+              sr.push_back(r);
+            }
+          }
+          op.flops += b.flops;
+          op.bytes_alg += b.bytes_alg;
+        }
+        op.toff = put(M, sa);
+        op.count = (int)sa.size();
+        if (o0.kind == OP_RANK) {
+          op.toff2 = put(M, sr);
+          op.count2 = (int)sr.size();
+        }
+        M.ops.push_back(op);
+        break;
+      }
+      case OP_FILL: {
+        std::vector<FillRec> r;
+        for (const auto& pr : grp) {
+          const FillRec* src = reinterpret_cast<const FillRec*>(tab(pr.first, pr.second->toff));
+          r.insert(r.end(), src, src + pr.second->count);
+        }
+        const char* l = g_label;
+        g_label = o0.label;
+        add_fills(M, r);
+        g_label = l;
+        break;
+      }
+      case OP_COPY: {
+        std::vector<CopyRec> r;
+        for (const auto& pr : grp) {
+          const CopyRec* src = reinterpret_cast<const CopyRec*>(tab(pr.first, pr.second->toff));
+          r.insert(r.end(), src, src + pr.second->count);
+        }
+        const char* l = g_label;
+        g_label = o0.label;
+        add_copies(M, r);
+        g_label = l;
+        break;
+      }
+      case OP_SETSTATE: case OP_ROOTNORM: case OP_WRITESCALE: {
+        std::vector<StateRec> r;
+        for (const auto& pr : grp) {
+          const StateRec* src = reinterpret_cast<const StateRec*>(tab(pr.first, pr.second->toff));
+          r.insert(r.end(), src, src + pr.second->count);
+        }
+        const char* l = g_label;
+        g_label = o0.label;
+        add_state(M, o0.kind, r);
+        g_label = l;
+        break;
+      }
+      default:
+        return fail(HT_EUNSUPPORTED, "batched plan: launch kind " + std::to_string(o0.kind) + " cannot be merged");
+    }
+  }
+  return HT_OK;
 }
 
 void build_key(Plan& P) {
@@ -375,9 +612,8 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
                        reinterpret_cast<GlobalState*>(op.p0));
         break;
       case OP_RANK:
-        e = launch_rank_select(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, op.i0, op.i1,
-                               op.f0, op.i2, op.i3, op.i4, op.i5, reinterpret_cast<GlobalState*>(op.p0),
-                               stream);
+        e = launch_rank_select(reinterpret_cast<const SmallArgs*>(tb + op.toff),
+                               reinterpret_cast<const StateRec*>(tb + op.toff2), op.count2, stream);
         break;
       case OP_PROJPREP:
         e = launch_proj_prep(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
@@ -388,19 +624,16 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
                                   reinterpret_cast<double* const*>(tb + op.bytes), stream);
         break;
       case OP_ROOTNORM:
-        e = launch_root_norm(reinterpret_cast<const double*>(op.p1), op.i0, op.i1,
-                             reinterpret_cast<GlobalState*>(op.p0), stream);
+        e = launch_root_norm(reinterpret_cast<const StateRec*>(tb + op.toff), op.count, stream);
         break;
       case OP_FILL:
-        e = launch_fill(op.p0, op.bytes, stream);
+        e = launch_fill(reinterpret_cast<const FillRec*>(tb + op.toff), op.count, op.bytes, stream);
         break;
       case OP_SETSTATE:
-        e = launch_set_state(reinterpret_cast<GlobalState*>(op.p0), op.scale0, stream);
+        e = launch_set_state(reinterpret_cast<const StateRec*>(tb + op.toff), op.count, stream);
         break;
       case OP_WRITESCALE:
-        e = launch_write_scale(reinterpret_cast<const GlobalState*>(op.p0), reinterpret_cast<long long*>(op.p1),
-                               reinterpret_cast<unsigned int*>(op.p2), reinterpret_cast<int*>(op.bytes ? (void*)op.bytes : nullptr),
-                               op.i0, stream);
+        e = launch_write_scale(reinterpret_cast<const StateRec*>(tb + op.toff), op.count, stream);
         break;
       case OP_EGATHER:
         e = launch_entry_gather(reinterpret_cast<const EntryNode*>(tb + op.toff), op.count, op.c[0],
@@ -414,8 +647,7 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
                                 op.c[0], op.scale0, reinterpret_cast<double*>(op.p2), stream);
         break;
       case OP_COPY:
-        e = launch_copy3(op.p0, op.i0, op.p1, op.i1, op.c[0], op.c[1], op.c[2], op.c[3], op.c[4], op.c[5],
-                         op.c[6], op.c[7], op.c[8], op.f0, stream);
+        e = launch_copy3(reinterpret_cast<const CopyRec*>(tb + op.toff), op.count, op.c[0], stream);
         break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -674,8 +906,9 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   // ---- launches
   g_label = "setup";
   {
-    Op op; op.kind = OP_SETSTATE; op.p0 = O.st; op.scale0 = S.scale0; op.label = g_label;
-    P.ops.push_back(op);
+    StateRec r = blank_state(O.st);
+    r.scale0 = S.scale0;
+    add_state(P, OP_SETSTATE, {r});
   }
   add_fill(P, zptr, zbytes);
 
@@ -735,6 +968,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       a.rf_type = T; a.tol_rel = tol;
       a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rank_dev = b.rank; a.scratch = b.scratch;
       a.Bh = b.Bh;
+      a.st = O.st;
       v.push_back(a);
     }
     return v;
@@ -889,10 +1123,19 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   g_label = "root_orth";
   // root: HD = blockdiag(alpha_c B_D^(c)); BDo = R_t1 HD R_t2^T
   const int t1 = tr.son1[0], t2 = tr.son2[0];
-  for (int c = 0; c < S.n_in; ++c) {
-    const int r1 = S.X[c]->rank[t1], r2 = S.X[c]->rank[t2];
-    add_copy(P, S.X[c]->transfer[0], F64, O.HD + (size_t)S.off[t1][c] * K2r + S.off[t2][c], F64, r1, r2, r2, 1,
-             K2r, 1, S.alpha[c]);
+  {
+    std::vector<CopyRec> cr;
+    for (int c = 0; c < S.n_in; ++c) {
+      const int r1 = S.X[c]->rank[t1], r2 = S.X[c]->rank[t2];
+      CopyRec q;
+      std::memset(&q, 0, sizeof(q));
+      q.src = S.X[c]->transfer[0]; q.tsrc = F64;
+      q.dst = O.HD + (size_t)S.off[t1][c] * K2r + S.off[t2][c]; q.tdst = F64;
+      q.n0 = 1; q.n1 = r1; q.n2 = r2; q.s1 = r2; q.s2 = 1; q.d1 = K2r; q.d2 = 1;
+      q.alpha = S.alpha[c];
+      cr.push_back(q);
+    }
+    add_copies(P, cr);
   }
   {
     std::vector<GemmDesc> a1, a2;
@@ -922,9 +1165,9 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
   const int K1r = K[t1], K2r = K[t2];
   g_label = "gramian_root";
   {
-    Op op; op.kind = OP_ROOTNORM; op.p0 = st; op.p1 = const_cast<double*>(BDo); op.i0 = K1r; op.i1 = K2r;
-    op.label = g_label;
-    P.ops.push_back(op);
+    StateRec r = blank_state(st);
+    r.BD = BDo; r.K1 = K1r; r.K2 = K2r;
+    add_state(P, OP_ROOTNORM, {r});
   }
   {
     std::vector<GemmDesc> a, b;
@@ -1106,6 +1349,7 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     a.rank_dev = out_ranks ? out_ranks + t : b.rank;
     a.scratch = b.scratch; a.Bh = b.Bh;
     a.sigma_out = out_sigma ? out_sigma + (size_t)t * KMAX : nullptr;
+    a.st = O.st;
     sa.push_back(a);
   }
   g_label = "eig";
@@ -1114,9 +1358,12 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
   g_label = "rank_select";
   add_small(P, OP_RANK, sa);
   {
+    StateRec r = blank_state(O.st);
+    r.a0 = 0; r.na = (int)sa.size(); r.d = d; r.mode = opts->mode; r.eps = opts->eps;
+    r.rel = opts->eps_relative ? 1 : 0; r.t1 = tr.son1[0]; r.t2 = tr.son2[0];
     Op& op = P.ops.back();
-    op.p0 = O.st; op.i0 = d; op.i1 = opts->mode; op.f0 = opts->eps; op.i2 = opts->eps_relative ? 1 : 0;
-    op.i3 = opts->max_rank; op.i4 = tr.son1[0]; op.i5 = tr.son2[0];
+    op.toff2 = put(P, std::vector<StateRec>{r});
+    op.count2 = 1;
   }
   g_label = "proj_prep";
   add_small(P, OP_PROJPREP, sa);
@@ -1204,9 +1451,10 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     add_gemm(P, r2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
   }
   {
-    Op op; op.kind = OP_WRITESCALE; op.p0 = O.st; op.p1 = out_scale; op.p2 = flags;
-    op.bytes = (size_t)(out_ranks ? (void*)out_ranks : nullptr);
-    P.ops.push_back(op);
+    g_label = "finish";
+    StateRec r = blank_state(O.st);
+    r.out_scale = reinterpret_cast<long long*>(out_scale); r.flags = flags; r.root_rank = out_ranks;
+    add_state(P, OP_WRITESCALE, {r});
   }
   (void)tsz;
   if (need) *need = align256(A.off) + 256;
@@ -1255,6 +1503,95 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
   return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
 }
 
+// ------------------------------------------------------------------ batched truncation
+// The plans of the tensors of a batch, each with its own part of the
+// workspace (need[c] bytes at offset off[c]), merged into one.
+static ht_status build_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
+                                        const double* coef, const ht_trunc_opts* opts, const ht_desc* out,
+                                        int32_t* const* out_ranks, int64_t* out_scale, uint32_t* flags,
+                                        double* const* out_sigma, void* ws, Plan& M, size_t* need) {
+  if (count < 1) return fail(HT_EINVAL, "count must be >= 1");
+  if (!X || !n_in || !opts) return fail(HT_EINVAL, "X, n_in or opts is NULL");
+  if (!need && (!out || !out_scale)) return fail(HT_EINVAL, "out or out_log2_scale is NULL");
+  std::vector<Plan> plans(count);
+  size_t off = 0, total = 0;
+  int64_t first = 0;
+  for (int c = 0; c < count; ++c) {
+    if (n_in[c] < 1) return fail(HT_EINVAL, "n_in[" + std::to_string(c) + "] must be >= 1");
+    const ht_desc* Xc = X + first;
+    size_t nc = 0;
+    Plan dry;
+    ht_status st = build_truncate(ctx, Xc, nullptr, n_in[c], &opts[c], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, dry, &nc);
+    if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
+    nc = align256(nc);
+    if (need) {
+      total += nc;
+    } else {
+      char* wc = reinterpret_cast<char*>(ws) + off;
+      st = build_truncate(ctx, Xc, coef ? coef + first : nullptr, n_in[c], &opts[c], &out[c],
+                          out_ranks ? out_ranks[c] : nullptr, out_scale + c, flags ? flags + c : nullptr,
+                          out_sigma ? out_sigma[c] : nullptr, wc, plans[c], nullptr);
+      if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
+    }
+    off += nc;
+    first += n_in[c];
+  }
+  if (need) {
+    *need = total;
+    return HT_OK;
+  }
+  return merge_plans(plans, M);
+}
+
+ht_status ht_truncate_batched_workspace(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
+                                        const ht_trunc_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(HT_EINVAL, "bytes is NULL");
+  if (count < 1 || !X || !n_in) return fail(HT_EINVAL, "count, X or n_in");
+  int64_t tot = 0;
+  for (int c = 0; c < count; ++c) {
+    if (n_in[c] < 1) return fail(HT_EINVAL, "n_in[" + std::to_string(c) + "] must be >= 1");
+    tot += n_in[c];
+  }
+  for (int64_t i = 0; i < tot; ++i) {
+    ht_status s = check_desc(&X[i], "X[i]", false);
+    if (s) return s;
+  }
+  // a dry run needs descriptors with data pointers; substitute placeholders
+  std::vector<ht_desc> Xs(X, X + tot);
+  std::vector<std::vector<void*>> leaves(tot), trans(tot);
+  std::vector<std::vector<int64_t>> lds(tot);
+  for (int64_t i = 0; i < tot; ++i) {
+    leaves[i].assign(X[i].d, (void*)256);
+    trans[i].assign(2 * X[i].d - 1, (void*)256);
+    lds[i].assign(X[i].n, X[i].n + X[i].d);
+    if (!X[i].leaf) Xs[i].leaf = leaves[i].data();
+    if (!X[i].transfer) Xs[i].transfer = trans[i].data();
+    if (!X[i].leaf_ld) Xs[i].leaf_ld = lds[i].data();
+  }
+  Plan M;
+  return build_truncate_batched(ctx, count, Xs.data(), n_in, nullptr, opts, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, M, bytes);
+}
+
+ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
+                              const double* coef, const ht_trunc_opts* opts, const ht_desc* out,
+                              int32_t* const* out_ranks, int64_t* out_log2_scale, uint32_t* flags,
+                              double* const* out_sigma, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  ht_status st = ht_truncate_batched_workspace(ctx, count, X, n_in, opts, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan M;
+  st = build_truncate_batched(ctx, count, X, n_in, coef, opts, out, out_ranks, out_log2_scale, flags, out_sigma,
+                              ws, M, nullptr);
+  if (st) return st;
+  return run_plan(ctx, M, reinterpret_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------------------ orthogonalisation
 static ht_status build_orth(const ht_desc* X, int precision, int64_t* out_scale, uint32_t* flags, void* ws,
                             Plan& P, size_t* need) {
@@ -1281,13 +1618,24 @@ static ht_status build_orth(const ht_desc* X, int precision, int64_t* out_scale,
     dq.push_back(g);
   }
   add_gemm(P, dq, X->frame_dtype, F64, F64, MATH_F64, GEMM_STORE, false, false);
-  for (int mu = 0; mu < X->d; ++mu) {
-    const int t = tr.leaf_node[mu];
-    add_copy(P, O.nb[t].Y, F64, X->leaf[mu], X->frame_dtype, X->n[mu], S.K[t], 1, X->n[mu], 1,
-             X->leaf_ld[mu], 1.0);
+  {
+    std::vector<CopyRec> cr;
+    for (int mu = 0; mu < X->d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      CopyRec q;
+      std::memset(&q, 0, sizeof(q));
+      q.src = O.nb[t].Y; q.tsrc = F64; q.dst = X->leaf[mu]; q.tdst = X->frame_dtype;
+      q.n0 = 1; q.n1 = X->n[mu]; q.n2 = S.K[t]; q.s1 = 1; q.s2 = X->n[mu]; q.d1 = 1; q.d2 = X->leaf_ld[mu];
+      q.alpha = 1.0;
+      cr.push_back(q);
+    }
+    add_copies(P, cr);
   }
-  Op op; op.kind = OP_WRITESCALE; op.p0 = O.st; op.p1 = out_scale; op.p2 = flags;
-  P.ops.push_back(op);
+  {
+    StateRec r = blank_state(O.st);
+    r.out_scale = reinterpret_cast<long long*>(out_scale); r.flags = flags;
+    add_state(P, OP_WRITESCALE, {r});
+  }
   if (need) *need = align256(A.off) + 256;
   return HT_OK;
 }
@@ -1361,11 +1709,15 @@ static ht_status build_gram(const ht_desc* X, double* const* bhat, double* const
     nb[t].scratch = (double*)A.take(eig_scratch_doubles(K[t]) * 8);
   }
   {
-    Op op; op.kind = OP_SETSTATE; op.p0 = st; op.scale0 = X->log2_scale;
-    P.ops.push_back(op);
+    StateRec r = blank_state(st);
+    r.scale0 = X->log2_scale;
+    add_state(P, OP_SETSTATE, {r});
   }
-  if (!need)
-    for (int t = 1; t < nn; ++t) add_fill(P, nb[t].Bh, (size_t)K[t] * K[t] * 8);
+  if (!need) {
+    std::vector<FillRec> fr;
+    for (int t = 1; t < nn; ++t) fr.push_back(FillRec{nb[t].Bh, (size_t)K[t] * K[t] * 8});
+    add_fills(P, fr);
+  }
   std::vector<const void*> Qo(nn, nullptr);
   for (int t = 1; t < nn; ++t) Qo[t] = X->transfer ? X->transfer[t] : nullptr;
   plan_gramians(P, tr, K, nb, (const double*)X->transfer[0], st, Qo, X->transfer_dtype);
@@ -1385,8 +1737,9 @@ static ht_status build_gram(const ht_desc* X, double* const* bhat, double* const
     P.ops.back().bytes = put(P, sp);
   }
   if (out_units) {
-    Op op; op.kind = OP_WRITESCALE; op.p0 = st; op.p1 = out_units; op.p2 = nullptr; op.i0 = 1;
-    P.ops.push_back(op);
+    StateRec r = blank_state(st);
+    r.out_scale = reinterpret_cast<long long*>(out_units); r.add_eD = 1;
+    add_state(P, OP_WRITESCALE, {r});
   }
   if (need) *need = align256(A.off) + 256;
   (void)z0;
@@ -1694,22 +2047,47 @@ void fake_tensor(FakeSpace& F, const ht_desc* X, const std::vector<int>& ranks, 
   T.desc.transfer = T.transfer.data();
 }
 
-bool inside(uintptr_t lo, uintptr_t hi, std::string* where) {
-  for (const auto& r : *g_regions)
-    if (lo >= r.lo && hi <= r.lo + r.bytes) { *where = r.what; return true; }
-  return false;
+// [lo, hi) lies inside one registered region: with the regions sorted by
+// start, some region that starts at or before lo must reach hi, i.e. the
+// largest end among them is >= hi (regions may nest, as the zero-filled
+// block around the accumulation targets does).
+struct RegionIndex {
+  const std::vector<Region>* src = nullptr;
+  size_t n = 0;
+  std::vector<uintptr_t> start, maxend;
+};
+static thread_local RegionIndex g_rindex;
+
+bool inside(uintptr_t lo, uintptr_t hi) {
+  RegionIndex& ix = g_rindex;
+  if (ix.src != g_regions || ix.n != g_regions->size()) {
+    std::vector<Region> v(*g_regions);
+    std::sort(v.begin(), v.end(), [](const Region& a, const Region& b) { return a.lo < b.lo; });
+    ix.start.resize(v.size());
+    ix.maxend.resize(v.size());
+    uintptr_t m = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      ix.start[i] = v[i].lo;
+      m = std::max<uintptr_t>(m, v[i].lo + v[i].bytes);
+      ix.maxend[i] = m;
+    }
+    ix.src = g_regions;
+    ix.n = g_regions->size();
+  }
+  const size_t i = std::upper_bound(ix.start.begin(), ix.start.end(), lo) - ix.start.begin();
+  return i > 0 && ix.maxend[i - 1] >= hi;
 }
 
 ht_status check_range(const void* base, int64_t lo_el, int64_t hi_el, int esz, const std::string& what) {
   if (!base) return fail(HT_EINVAL, "validator: NULL pointer in " + what);
   const uintptr_t b = reinterpret_cast<uintptr_t>(base);
   const uintptr_t lo = b + (uintptr_t)(lo_el * esz), hi = b + (uintptr_t)((hi_el + 1) * esz);
-  std::string where;
-  if (!inside(lo, hi, &where)) return fail(HT_EINVAL, "validator: out-of-bounds access in " + what);
+  if (!inside(lo, hi)) return fail(HT_EINVAL, "validator: out-of-bounds access in " + what);
   return HT_OK;
 }
 
 ht_status validate_plan(const Plan& P, int64_t m_entries) {
+  g_rindex = RegionIndex();   // the regions are complete now: index them afresh
   auto at = [&](size_t off) { return P.table.data() + off; };
   int opi = 0;
   for (const auto& op : P.ops) {
@@ -1799,16 +2177,38 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         }
       }
     } else if (op.kind == OP_FILL) {
-      if ((s = check_range(op.p0, 0, (int64_t)op.bytes / 4 - 1, 4, tag + " fill"))) return s;
+      const FillRec* fr = reinterpret_cast<const FillRec*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        if (fr[i].bytes > op.bytes || (fr[i].bytes & 3)) return fail(HT_EINVAL, "validator: fill size " + tag);
+        if (fr[i].bytes && (s = check_range(fr[i].p, 0, (int64_t)fr[i].bytes / 4 - 1, 4, tag + " fill"))) return s;
+      }
     } else if (op.kind == OP_COPY) {
-      const int64_t n0 = op.c[0], n1 = op.c[1], n2 = op.c[2];
-      if (n0 * n1 * n2 == 0) continue;
-      if ((s = check_range(op.p0, 0, (n0 - 1) * op.c[3] + (n1 - 1) * op.c[4] + (n2 - 1) * op.c[5], esize(op.i0),
-                           tag + " copy src")))
-        return s;
-      if ((s = check_range(op.p1, 0, (n0 - 1) * op.c[6] + (n1 - 1) * op.c[7] + (n2 - 1) * op.c[8], esize(op.i1),
-                           tag + " copy dst")))
-        return s;
+      const CopyRec* cr = reinterpret_cast<const CopyRec*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const CopyRec& c = cr[i];
+        const int64_t n0 = c.n0, n1 = c.n1, n2 = c.n2;
+        if (n0 * n1 * n2 > op.c[0]) return fail(HT_EINVAL, "validator: copy size " + tag);
+        if (n0 * n1 * n2 == 0) continue;
+        if ((s = check_range(c.src, 0, (n0 - 1) * c.s0 + (n1 - 1) * c.s1 + (n2 - 1) * c.s2, esize(c.tsrc),
+                             tag + " copy src")))
+          return s;
+        if ((s = check_range(c.dst, 0, (n0 - 1) * c.d0 + (n1 - 1) * c.d1 + (n2 - 1) * c.d2, esize(c.tdst),
+                             tag + " copy dst")))
+          return s;
+      }
+    } else if (op.kind == OP_SETSTATE || op.kind == OP_WRITESCALE || op.kind == OP_ROOTNORM) {
+      const StateRec* sr = reinterpret_cast<const StateRec*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const StateRec& r = sr[i];
+        if ((s = check_range(r.st, 0, 0, sizeof(GlobalState), tag + " state"))) return s;
+        if (op.kind == OP_ROOTNORM && (s = check_range(r.BD, 0, (int64_t)r.K1 * r.K2 - 1, 8, tag + " root")))
+          return s;
+        if (op.kind == OP_WRITESCALE) {
+          if (r.out_scale && (s = check_range(r.out_scale, 0, 0, 8, tag + " scale"))) return s;
+          if (r.flags && (s = check_range(r.flags, 0, 0, 4, tag + " flags"))) return s;
+          if (r.root_rank && (s = check_range(r.root_rank, 0, 0, 4, tag + " ranks"))) return s;
+        }
+      }
     } else if (op.kind == OP_EGATHER || op.kind == OP_ENORM) {
       const EntryNode* en = reinterpret_cast<const EntryNode*>(at(op.toff));
       const int64_t mc = op.c[0];
@@ -1827,8 +2227,14 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
       if ((s = check_range(op.p0, 0, op.c[0] - 1, 8, tag + " vals")) || (s = check_range(op.p1, 0, op.c[0] - 1, 4, tag + " expo")) ||
           (s = check_range(op.p2, 0, op.c[0] - 1, 8, tag + " out")))
         return s;
-    } else if (op.kind == OP_ROOTNORM) {
-      if ((s = check_range(op.p1, 0, (int64_t)op.i0 * op.i1 - 1, 8, tag + " root"))) return s;
+    }
+    if (op.kind == OP_RANK) {   // each tensor's node range lies inside the launch's arguments
+      const StateRec* sr = reinterpret_cast<const StateRec*>(at(op.toff2));
+      for (int i = 0; i < op.count2; ++i) {
+        if (sr[i].a0 < 0 || sr[i].na < 1 || sr[i].a0 + sr[i].na > op.count)
+          return fail(HT_EINVAL, "validator: rank range " + tag);
+        if ((s = check_range(sr[i].st, 0, 0, sizeof(GlobalState), tag + " state"))) return s;
+      }
     }
   }
   (void)m_entries;
@@ -1837,8 +2243,8 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
 
 struct RegionScope {
   std::vector<Region> regions;
-  RegionScope() { g_regions = &regions; }
-  ~RegionScope() { g_regions = nullptr; }
+  RegionScope() { g_regions = &regions; g_rindex = RegionIndex(); }
+  ~RegionScope() { g_regions = nullptr; g_rindex = RegionIndex(); }
 };
 
 }  // namespace
@@ -1882,6 +2288,68 @@ ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_tr
                       (uint32_t*)flags, (double*)sigma, ws, P, nullptr);
   if (st) return st;
   return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_truncate_batched(int32_t count, const ht_desc* X, const int32_t* n_in,
+                                             const ht_trunc_opts* opts, int32_t* n_launches) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_truncate_batched_workspace(nullptr, count, X, n_in, opts, &need);
+  if (st) return st;
+  FakeSpace F;
+  int64_t tot = 0;
+  for (int c = 0; c < count; ++c) tot += n_in[c];
+  std::vector<FakeTensor> fx(tot), fo(count);
+  std::vector<ht_desc> xs(tot), outs(count);
+  std::vector<int32_t*> ranks(count);
+  std::vector<double*> sigma(count);
+  int64_t first = 0;
+  for (int c = 0; c < count; ++c) {
+    const int d = X[first].d;
+    Tree tr(d);
+    for (int i = 0; i < n_in[c]; ++i) {
+      const ht_desc& Xi = X[first + i];
+      std::vector<int> rk(Xi.rank, Xi.rank + tr.nn);
+      fake_tensor(F, &Xi, rk, Xi.frame_dtype, Xi.transfer_dtype, fx[first + i], "X");
+      xs[first + i] = fx[first + i].desc;
+    }
+    SumInfo S;
+    if ((st = sum_info(xs.data() + first, nullptr, n_in[c], S))) return st;
+    const ht_trunc_opts& o = opts[c];
+    std::vector<int> rc(tr.nn, 1);
+    for (int t = 1; t < tr.nn; ++t)
+      rc[t] = o.mode == HT_RANK_FIXED ? std::min(o.ranks[t], S.K[t])
+                                      : (o.max_rank > 0 ? std::min(o.max_rank, S.K[t]) : S.K[t]);
+    if (o.mode == HT_RANK_TOL) rc[tr.son1[0]] = rc[tr.son2[0]] = std::min(rc[tr.son1[0]], rc[tr.son2[0]]);
+    const int T = o.precision == HT_PREC_MIXED ? HT_F32 : HT_F64;
+    fake_tensor(F, &X[first], rc, T, T, fo[c], "out");
+    outs[c] = fo[c].desc;
+    ranks[c] = (int32_t*)F.get((size_t)tr.nn * 4, "out_ranks");
+    sigma[c] = (double*)F.get((size_t)tr.nn * KMAX * 8, "sigma");
+    first += n_in[c];
+  }
+  void* scale = F.get((size_t)count * 8, "out_scale");
+  void* flags = F.get((size_t)count * 4, "flags");
+  // the workspace: one region per problem, as the library lays it out
+  std::vector<size_t> part(count);
+  first = 0;
+  for (int c = 0; c < count; ++c) {
+    if ((st = ht_truncate_workspace(nullptr, xs.data() + first, n_in[c], &opts[c], &part[c]))) return st;
+    part[c] = align256(part[c]);
+    first += n_in[c];
+  }
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  size_t acc = 0;
+  for (int c = 0; c < count; ++c) acc += part[c];
+  if (acc != need) return fail(HT_EINVAL, "validator: batched workspace size differs from the sum of its parts");
+  Plan M;
+  std::vector<double> coef(tot, 1.0);
+  st = build_truncate_batched(nullptr, count, xs.data(), n_in, coef.data(), opts, outs.data(), ranks.data(),
+                              (int64_t*)scale, (uint32_t*)flags, sigma.data(), ws, M, nullptr);
+  if (st) return st;
+  if (n_launches) *n_launches = (int32_t)M.ops.size();
+  return validate_plan(M, 0);
 }
 
 ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision) {

@@ -43,6 +43,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   __shared__ int dropped[KMAX];
   __shared__ int any;
   const SmallArgs& a = args[blockIdx.x];
+  if (a.st) st = a.st;
   const int K = a.K;
   const int NB = (K + 15) >> 4, Kp = NB * 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -234,6 +235,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 __global__ __launch_bounds__(NT) void finish_r_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
   __shared__ double red[NT / 64];
   const SmallArgs& a = args[blockIdx.x];
+  if (a.st) st = a.st;
   const int K = a.K;
   const int tid = threadIdx.x;
   double mx = 0.0;

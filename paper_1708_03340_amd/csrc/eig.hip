@@ -63,6 +63,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
   __shared__ int rankpos[KMAX];
   __shared__ int sh_iters;
   const SmallArgs& a = args[blockIdx.x];
+  if (a.st) st = a.st;
   const int K = a.K, ld = K + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ty = tid >> 4, tx = tid & 15;

@@ -121,6 +121,7 @@ struct SmallArgs {
   double* sigma_out;       // optional: 128 slots for sigma / ||A||
   double* scratch;         // eigensolver scratch, 3 K^2 doubles
   double* Bh;              // K x K Gramian (eigensolver input)
+  struct GlobalState* st;  // state of the tensor this node belongs to (NULL: the launch's)
 };
 
 struct GlobalState {       // device-resident per-call scalars
@@ -133,23 +134,41 @@ struct GlobalState {       // device-resident per-call scalars
   double thr;              // tolerance threshold in Gramian units
 };
 
-hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);   // bytes: multiple of 4
-hipError_t launch_set_state(GlobalState* st, long long scale0, hipStream_t s);
+// One tensor's scalars for the state kernels; a launch takes an array of
+// them, one per tensor of a batch.
+struct StateRec {
+  GlobalState* st;
+  long long scale0;        // set_state: initial binary exponent of the tensor
+  const double* BD;        // root_norm: root matrix K1 x K2, row-major
+  int32_t K1, K2;
+  long long* out_scale;    // write_scale targets (each may be NULL)
+  unsigned int* flags;
+  int32_t* root_rank;
+  int32_t add_eD;          // write_scale: add the root exponent e_D
+  int32_t a0, na;          // rank selection: the tensor's nodes are args[a0 .. a0+na)
+  int32_t d, mode, rel, t1, t2, pad;   // order, rank mode, relative eps, sons of the root
+  double eps;
+};
+struct FillRec { void* p; size_t bytes; };   // zero p[0 .. bytes), bytes a multiple of 4
+// dst[i*d0 + j*d1 + k*d2] = alpha * src[i*s0 + j*s1 + k*s2] over n0 x n1 x n2
+struct CopyRec {
+  const void* src;
+  void* dst;
+  int32_t tsrc, tdst;
+  int64_t n0, n1, n2, s0, s1, s2, d0, d1, d2;
+  double alpha;
+};
+
+hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s);
+hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);
 hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st);
 hipError_t launch_eig(const SmallArgs* args, int n, double* scratch, hipStream_t s, GlobalState* st);
-hipError_t launch_rank_select(const SmallArgs* args, int n, int d, int mode, double eps, int rel,
-                              int max_rank, int t1, int t2, GlobalState* st, hipStream_t s);
+hipError_t launch_rank_select(const SmallArgs* args, const StateRec* r, int n, hipStream_t s);
 hipError_t launch_proj_prep(const SmallArgs* args, int n, const GlobalState* st, hipStream_t s);
-hipError_t launch_root_norm(const double* BD, int K1, int K2, GlobalState* st, hipStream_t s);
-hipError_t launch_copy_root(const double* src, int rows, int cols, int ld_src, double alpha,
-                            double* dst, int ld_dst, hipStream_t s);
-hipError_t launch_write_scale(const GlobalState* st, long long* out_scale, unsigned int* flags,
-                              int* root_rank, int add_eD, hipStream_t s);
-// dst[i*d0 + j*d1 + k*d2] = alpha * src[i*s0 + j*s1 + k*s2] over n0 x n1 x n2
-hipError_t launch_copy3(const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
-                        int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2,
-                        double alpha, hipStream_t s);
+hipError_t launch_root_norm(const StateRec* r, int n, hipStream_t s);
+hipError_t launch_write_scale(const StateRec* r, int n, hipStream_t s);
+hipError_t launch_copy3(const CopyRec* r, int n, int64_t max_elems, hipStream_t s);
 hipError_t launch_sigma_from_lam(const SmallArgs* args, int n, double* const* sigma_ptrs,
                                  hipStream_t s);
 

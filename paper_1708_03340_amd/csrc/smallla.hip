@@ -14,10 +14,15 @@ constexpr int NT = DNT;
 
 
 // ------------------------------------------------------------------ ranks
-__global__ void rank_kernel(const SmallArgs* __restrict__ args, int n, int d, int mode, double eps,
-                            int rel, int t1, int t2, GlobalState* st) {
+// One workgroup per tensor: its nodes are args[a0 .. a0 + na).
+__global__ void rank_kernel(const SmallArgs* __restrict__ all_args, const StateRec* __restrict__ recs) {
   __shared__ double red[NT / 64];
   __shared__ int idx_t1, idx_t2;
+  const StateRec& R = recs[blockIdx.x];
+  const SmallArgs* args = all_args + R.a0;
+  const int n = R.na, d = R.d, mode = R.mode, t1 = R.t1, t2 = R.t2;
+  const double eps = R.eps;
+  GlobalState* st = R.st;
   const int tid = threadIdx.x;
   // ||A||^2 in Gramian units: trace of Bhat_t1 = sum of its eigenvalues
   if (tid == 0) { idx_t1 = -1; idx_t2 = -1; }
@@ -32,7 +37,7 @@ __global__ void rank_kernel(const SmallArgs* __restrict__ args, int n, int d, in
     for (int i = tid; i < args[idx_t1].K; i += NT) part += args[idx_t1].lam[i];
   const double n2 = wg_sum(part, red);
   double thr;
-  if (rel) {
+  if (R.rel) {
     thr = eps * eps * n2 / (double)(2 * d - 3);
   } else {
     const long long g = st->e_D + st->log2_scale;
@@ -74,6 +79,7 @@ __global__ void rank_kernel(const SmallArgs* __restrict__ args, int n, int d, in
 // forward-product type; optional sigma / ||A||.
 __global__ void proj_prep_kernel(const SmallArgs* __restrict__ args, const GlobalState* st) {
   const SmallArgs& a = args[blockIdx.x];
+  if (a.st) st = a.st;
   const int K = a.K, rc = a.rcap;
   const int r = *a.rank_dev;
   for (int idx = threadIdx.x; idx < K * rc; idx += blockDim.x) {
@@ -100,13 +106,21 @@ __global__ void sigma_kernel(const SmallArgs* __restrict__ args, double* const* 
 }
 
 // ------------------------------------------------------------------ misc
-__global__ void fill_kernel(uint32_t* p, size_t n) {
+// Zero fills, copies and the state kernels take one record per region or
+// tensor: blockIdx.y (fills, copies) or the global thread index (state).
+__global__ void fill_kernel(const FillRec* __restrict__ recs) {
+  const FillRec& r = recs[blockIdx.y];
+  uint32_t* p = reinterpret_cast<uint32_t*>(r.p);
+  const size_t n = r.bytes / 4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = 0u;
 }
 
-__global__ void set_state_kernel(GlobalState* st, long long scale0) {
-  st->log2_scale = scale0;
+__global__ void set_state_kernel(const StateRec* __restrict__ recs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  GlobalState* st = recs[i].st;
+  st->log2_scale = recs[i].scale0;
   st->flags = 0;
   st->pad = 0;
   st->alpha_gram = 1.0;
@@ -115,11 +129,14 @@ __global__ void set_state_kernel(GlobalState* st, long long scale0) {
   st->thr = 0.0;
 }
 
-__global__ void root_norm_kernel(const double* BD, int K1, int K2, GlobalState* st) {
+__global__ void root_norm_kernel(const StateRec* __restrict__ recs) {
   __shared__ double red[NT / 64];
+  const StateRec& R = recs[blockIdx.x];
+  const double* BD = R.BD;
+  const int nel = R.K1 * R.K2;
   double s = 0.0;
   bool bad = false;
-  for (int i = threadIdx.x; i < K1 * K2; i += NT) {
+  for (int i = threadIdx.x; i < nel; i += NT) {
     const double v = BD[i];
     if (!isfinite(v)) bad = true;
     s += v * v;
@@ -128,51 +145,60 @@ __global__ void root_norm_kernel(const double* BD, int K1, int K2, GlobalState* 
   const double b = wg_max(bad ? 1.0 : 0.0, red);
   if (threadIdx.x == 0) {
     const int e = exp2_of(sqrt(tot));
-    st->e_D = e;
-    st->alpha_gram = ldexp(1.0, -2 * e);
-    if (b > 0.0) atomicOr(&st->flags, 2u);
+    R.st->e_D = e;
+    R.st->alpha_gram = ldexp(1.0, -2 * e);
+    if (b > 0.0) atomicOr(&R.st->flags, 2u);
   }
 }
 
-__global__ void write_scale_kernel(const GlobalState* st, long long* out, unsigned int* flags,
-                                   int* root_rank, int add_eD) {
-  if (out) *out = st->log2_scale + (add_eD ? st->e_D : 0);
-  if (flags) *flags = st->flags | ((unsigned)min(st->pad, 255) << 8);
-  if (root_rank) *root_rank = 1;
+__global__ void write_scale_kernel(const StateRec* __restrict__ recs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const StateRec& R = recs[i];
+  const GlobalState* st = R.st;
+  if (R.out_scale) *R.out_scale = st->log2_scale + (R.add_eD ? st->e_D : 0);
+  if (R.flags) *R.flags = st->flags | ((unsigned)min(st->pad, 255) << 8);
+  if (R.root_rank) *R.root_rank = 1;
 }
 
-__global__ void copy3_kernel(const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1,
-                             int64_t n2, int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1,
-                             int64_t d2, double alpha) {
-  const int64_t n = n0 * n1 * n2;
+__global__ void copy3_kernel(const CopyRec* __restrict__ recs) {
+  const CopyRec& R = recs[blockIdx.y];
+  const int64_t n1 = R.n1, n2 = R.n2;
+  const int64_t n = R.n0 * n1 * n2;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = i / (n1 * n2), r = (i / n2) % n1, c = i % n2;
-    const int64_t so = a * s0 + r * s1 + c * s2, dof = a * d0 + r * d1 + c * d2;
-    const double v = alpha * (tsrc == F64 ? reinterpret_cast<const double*>(src)[so]
-                                          : (double)reinterpret_cast<const float*>(src)[so]);
-    if (tdst == F64) reinterpret_cast<double*>(dst)[dof] = v;
-    else reinterpret_cast<float*>(dst)[dof] = (float)v;
+    const int64_t so = a * R.s0 + r * R.s1 + c * R.s2, dof = a * R.d0 + r * R.d1 + c * R.d2;
+    const double v = R.alpha * (R.tsrc == F64 ? reinterpret_cast<const double*>(R.src)[so]
+                                              : (double)reinterpret_cast<const float*>(R.src)[so]);
+    if (R.tdst == F64) reinterpret_cast<double*>(R.dst)[dof] = v;
+    else reinterpret_cast<float*>(R.dst)[dof] = (float)v;
   }
 }
+
+constexpr int kMaxY = 65535;   // records per launch along blockIdx.y
 
 }  // namespace
 
-hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s) {
-  const size_t n = bytes / 4;
-  if (n == 0) return hipSuccess;
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint32_t*>(ptr), n);
+hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s) {
+  const size_t m = max_bytes / 4;
+  if (n <= 0 || m == 0) return hipSuccess;
+  const int bx = (int)std::min<size_t>((m + 255) / 256, 4096);
+  for (int i0 = 0; i0 < n; i0 += kMaxY) {
+    const int ny = std::min(kMaxY, n - i0);
+    hipLaunchKernelGGL(fill_kernel, dim3(bx, ny), dim3(256), 0, s, r + i0);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_set_state(GlobalState* st, long long scale0, hipStream_t s) {
-  hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, scale0);
+hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_state_kernel, dim3((n + 63) / 64), dim3(64), 0, s, r, n);
   return hipGetLastError();
 }
 
-hipError_t launch_rank_select(const SmallArgs* args, int n, int d, int mode, double eps, int rel,
-                              int, int t1, int t2, GlobalState* st, hipStream_t s) {
-  hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(NT), 0, s, args, n, d, mode, eps, rel, t1, t2, st);
+hipError_t launch_rank_select(const SmallArgs* args, const StateRec* r, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_kernel, dim3(n), dim3(NT), 0, s, args, r);
   return hipGetLastError();
 }
 
@@ -188,25 +214,25 @@ hipError_t launch_sigma_from_lam(const SmallArgs* args, int n, double* const* si
   return hipGetLastError();
 }
 
-hipError_t launch_root_norm(const double* BD, int K1, int K2, GlobalState* st, hipStream_t s) {
-  hipLaunchKernelGGL(root_norm_kernel, dim3(1), dim3(NT), 0, s, BD, K1, K2, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_write_scale(const GlobalState* st, long long* out, unsigned int* flags, int* root_rank,
-                              int add_eD, hipStream_t s) {
-  hipLaunchKernelGGL(write_scale_kernel, dim3(1), dim3(1), 0, s, st, out, flags, root_rank, add_eD);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy3(const void* src, int tsrc, void* dst, int tdst, int64_t n0, int64_t n1, int64_t n2,
-                        int64_t s0, int64_t s1, int64_t s2, int64_t d0, int64_t d1, int64_t d2, double alpha,
-                        hipStream_t s) {
-  const int64_t n = n0 * n1 * n2;
+hipError_t launch_root_norm(const StateRec* r, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(copy3_kernel, dim3(blocks), dim3(256), 0, s, src, tsrc, dst, tdst, n0, n1, n2, s0, s1,
-                     s2, d0, d1, d2, alpha);
+  hipLaunchKernelGGL(root_norm_kernel, dim3(n), dim3(NT), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_scale(const StateRec* r, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(write_scale_kernel, dim3((n + 63) / 64), dim3(64), 0, s, r, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy3(const CopyRec* r, int n, int64_t max_elems, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0) return hipSuccess;
+  const int bx = (int)std::min<int64_t>((max_elems + 255) / 256, 4096);
+  for (int i0 = 0; i0 < n; i0 += kMaxY) {
+    const int ny = std::min(kMaxY, n - i0);
+    hipLaunchKernelGGL(copy3_kernel, dim3(bx, ny), dim3(256), 0, s, r + i0);
+  }
   return hipGetLastError();
 }
 

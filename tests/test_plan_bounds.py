@@ -20,7 +20,9 @@ def L():
     L.ht_debug_validate_orthogonalize.argtypes = [P(H.HtDesc), ctypes.c_int32]
     L.ht_debug_validate_gramians.argtypes = [P(H.HtDesc)]
     L.ht_debug_validate_entries.argtypes = [P(H.HtDesc), ctypes.c_int64]
-    for f in ("truncate", "orthogonalize", "gramians", "entries"):
+    L.ht_debug_validate_truncate_batched.argtypes = [ctypes.c_int32, P(H.HtDesc), P(ctypes.c_int32),
+                                                     P(H.HtTruncOpts), P(ctypes.c_int32)]
+    for f in ("truncate", "orthogonalize", "gramians", "entries", "truncate_batched"):
         getattr(L, "ht_debug_validate_" + f).restype = ctypes.c_int
     return L
 
@@ -116,3 +118,73 @@ def test_validator_catches_overrun(L):
     X = (H.HtDesc * 1)(desc(d, 10, uniform(d, 65)))
     o = opts(d, 0, [1] + [200] * (2 * d - 2))
     check(L, L.ht_debug_validate_truncate(X, 1, ctypes.byref(o)))   # ranks clamp to K
+
+
+def batch_problems(rng, count, kmax=48, mixed_modes=False):
+    """The batched workload's shapes: d in 4..32, n in [100, 4096], k in 8..48,
+    each tensor summed with a partner of its own shape, truncated to its k."""
+    xs, n_in, ops = [], [], []
+    for c in range(count):
+        d = int(rng.integers(4, 33))
+        n = int(rng.integers(100, 4097))
+        k = int(rng.integers(8, kmax + 1))
+        m = 2 if not mixed_modes else int(rng.integers(1, 4))
+        k = min(k, 128 // m)
+        fdt = H.HT_F32 if not mixed_modes else int(rng.integers(0, 2))
+        for _ in range(m):
+            xs.append(desc(d, n, uniform(d, k), fdt=fdt))
+        n_in.append(m)
+        mode = 0 if not mixed_modes else int(rng.integers(0, 2))
+        prec = H.HT_PREC_MIXED if not mixed_modes else int(rng.integers(0, 2))
+        ops.append(opts(d, mode, uniform(d, k), prec=prec))
+    X = (H.HtDesc * len(xs))(*xs)
+    N = (ctypes.c_int32 * count)(*n_in)
+    Op = (H.HtTruncOpts * count)(*ops)
+    return X, N, Op, (xs, ops)
+
+
+def test_batched_plan_in_bounds(L):
+    import numpy as np
+    X, N, Op, keep = batch_problems(np.random.default_rng(11), 48)
+    nl = ctypes.c_int32(0)
+    check(L, L.ht_debug_validate_truncate_batched(48, X, N, Op, ctypes.byref(nl)))
+    # one launch per step of the deepest tree, not per tensor: a d = 32 tree
+    # alone takes about 60; the state, copy and fill steps merge too
+    assert nl.value < 200, nl.value
+
+
+def test_batched_plan_mixed_problems_in_bounds(L):
+    """Different d, n, ranks, dtypes, summand counts, rank modes and precisions in one batch."""
+    import numpy as np
+    rng = np.random.default_rng(12)
+    for trial in range(6):
+        cnt = int(rng.integers(1, 24))
+        X, N, Op, keep = batch_problems(rng, cnt, mixed_modes=True)
+        check(L, L.ht_debug_validate_truncate_batched(cnt, X, N, Op, None))
+
+
+def test_batched_workspace_is_sum_of_parts(L):
+    import numpy as np
+    X, N, Op, keep = batch_problems(np.random.default_rng(13), 9)
+    need = ctypes.c_size_t(0)
+    check(L, H.lib().ht_truncate_batched_workspace(None, 9, X, N, Op, ctypes.byref(need)))
+    tot, o = 0, 0
+    for c in range(9):
+        part = ctypes.c_size_t(0)
+        check(L, H.lib().ht_truncate_workspace(None, ctypes.cast(ctypes.byref(X[o]), ctypes.POINTER(H.HtDesc)),
+                                               N[c], ctypes.byref(Op[c]), ctypes.byref(part)))
+        tot += (part.value + 255) // 256 * 256
+        o += N[c]
+    assert need.value == tot
+
+
+def test_batched_rejects_bad_problem(L):
+    """A shape error in one problem is reported with the problem's index."""
+    import numpy as np
+    X, N, Op, keep = batch_problems(np.random.default_rng(14), 3)
+    keep[1][1]._keep[0]  # options of problem 1 stay alive
+    Op[1].mode = 7
+    need = ctypes.c_size_t(0)
+    st = H.lib().ht_truncate_batched_workspace(None, 3, X, N, Op, ctypes.byref(need))
+    assert st != 0
+    assert "tensor 1" in L.ht_last_error().decode()
