@@ -169,10 +169,12 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
     bool ok = math == MATH_F64 && mode == GEMM_STORE;
     int swap = -1;
     long long items = 0;
+    bool k64 = true;
     for (const auto& d : descs) {
       int kt = 0;
       if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
       else kt = d.K;
+      if (kt % 64) k64 = false;
       if (d.kr || d.KB != 1 || kt < 1 || kt > 128) { ok = false; break; }
       const long long nbt = d.nbatch;
       const bool c0 = d.M <= 128 && d.sBn == 1 && d.N * nbt >= 256;   // S = A, T = B
@@ -188,6 +190,7 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
       big = false;
       op.g.sb_swap = swap == 1;
       op.g.sb_wn = 1;
+      op.g.sb_cd = k64 ? 64 : 32;
       const long long per = (512 + (long long)descs.size() - 1) / (long long)descs.size();
       op.g.sb_grid = (int)std::max<long long>(1, std::min(per, items));
     }
@@ -666,7 +669,7 @@ std::string kernel_name(const Op& op) {
     case OP_GEMM:   // the template arguments of the kernel that launch_gemm picks
       if (op.g.sb) {
         const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
-        return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + "," + std::to_string(op.g.sb_wn == 2 ? 2 : 1) +
+        return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + ",1," + std::to_string(op.g.sb_cd == 64 ? 64 : 32) +
                ">";
       }
       if (op.g.rk) {
@@ -1059,7 +1062,6 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     g_label = "inner_mode3_R";
     add_gemm(P, d3, tdt, T, T, fmath, GEMM_STORE, true, true, true);
     g_label = "inner_mode2_R";
-    g_label = "proj_inner_mode2";
     add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
     // sweep 1: G = M1(Bp) M1(Bp)^T in float64
     std::vector<GemmDesc> dg;
@@ -1425,7 +1427,6 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false, true);
     g_label = "proj_inner_mode1";
     add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false, true);
-    g_label = "inner_mode2_R";
     g_label = "proj_inner_mode2";
     add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
     g_label = "proj_inner_mode3";

@@ -39,7 +39,6 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   __shared__ double L[KMAX * LDL];            // A, then R (upper blocks) and X^T (lower blocks)
   __shared__ double Xd[KMAX / 16][16 * LDD];  // inverses of the diagonal blocks of R
   __shared__ double red[NT / 64];
-  __shared__ double piv[KMAX];
   __shared__ int dropped[KMAX];
   __shared__ int any;
   const SmallArgs& a = args[blockIdx.x];
@@ -58,8 +57,12 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
+        // every load is issued (clamped address, masked value): a guarded
+        // load would wait for each one in turn; identity on the padding
         const int r = r0 + 4 * u, c = lane + 64 * h;
-        v[u][h] = (r < K && c < K) ? gld(&Gin[r * K + c]) : (r == c ? 1.0 : 0.0);   // identity on the padding
+        const bool in = r < K && c < K;
+        const double g = gld(&Gin[min(r, K - 1) * K + min(c, K - 1)]);
+        v[u][h] = g * (in ? 1.0 : 0.0) + ((!in && r == c) ? 1.0 : 0.0);
       }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -87,47 +90,62 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 
   for (int p = 0; p < NB; ++p) {
     double* D = &L[16 * p * LDL + 16 * p];
-    // ---- diagonal block: unblocked Cholesky by wave 0 (lane: row l16,
-    // columns 4 l4 .. 4 l4 + 3), then the inverse of its factor
+    // ---- diagonal block, by wave 0 in registers: lane r (mod 16) holds row r
+    // of the block and row r of the elimination matrix E (E A = U, unit lower
+    // triangular).  Pivot j and row j reach every lane by readlane; the rank-1
+    // updates are register FMAs.  Then R_pp = D^{-1/2} U and, from E U^T = D,
+    // X_pp = R_pp^{-1} = E^T D^{-1/2} (D: the pivots).  A block with a dropped
+    // pivot gets its inverse by back substitution instead (unit rows there).
     if (wave == 0) {
+      const int r = l16;
+      double ar[16], er[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        ar[c] = D[r * LDL + c];
+        er[c] = c == r ? 1.0 : 0.0;
+      }
+      double rs = 1.0;
+      bool blockdrop = false, mydrop = false;
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int g = 16 * p + j;
-        double pj = D[j * LDL + j];
+        double pj = lane_val(ar[j], j);
         bool drop = false;
         if (g >= K) pj = 1.0;   // padding
         else if (!(pj > tol)) {
           if (sweep == 1) pj = tol; else drop = true;
         }
         if (lane == 0) {
-          piv[g] = drop ? 0.0 : pj;
           dropped[g] = drop ? 1 : 0;
           if (drop) any = 1;
         }
-        if (!drop) {
-          const double mult = D[l16 * LDL + j] * rcp_nr(pj);
-          double upd[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) upd[u] = D[l16 * LDL + 4 * l4 + u] - mult * D[j * LDL + 4 * l4 + u];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int c = 4 * l4 + u;
-            if (l16 > j && c > j) D[l16 * LDL + c] = upd[u];
-          }
+        if (drop) {
+          blockdrop = true;
+          mydrop = mydrop || r == j;
+          continue;
         }
+        const double ip = rcp_nr(pj);
+        if (r == j) {
+          rs = rsqrt_nr(pj);
+          ar[j] = pj;   // U_jj is the (possibly clamped) pivot
+        }
+        const double m = r > j ? ar[j] * ip : 0.0;
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-m, lane_val(ar[c], j), ar[c]);
+#pragma unroll
+        for (int c = 0; c <= j; ++c) er[c] = fma(-m, lane_val(er[c], j), er[c]);
       }
-      // scale the rows: R_pp (zero below the diagonal and on dropped rows)
+      if (lane < 16) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = l16, c = 4 * l4 + u, g = 16 * p + r;
-        double v = 0.0;
-        if (!dropped[g] && c >= r) {
-          const double s = sqrt(piv[g]);
-          v = c == r ? s : D[r * LDL + c] / s;
+        for (int c = 0; c < 16; ++c) D[r * LDL + c] = (c >= r && !mydrop) ? ar[c] * rs : 0.0;
+        if (!blockdrop) {
+          // column r of X_pp: X[i][r] = E[r][i] / sqrt(d_r)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) Xd[p][i * LDD + r] = i <= r ? er[i] * rs : 0.0;
         }
-        D[r * LDL + c] = v;
       }
       // X_pp = R_pp^{-1} (unit diagonal on dropped rows), lanes 0..15 one column each
-      if (lane < 16) {
+      if (blockdrop && lane < 16) {
         const int c = lane;
         double x[16];
 #pragma unroll
@@ -189,10 +207,11 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   // ---- R out (upper blocks of L; zero below the diagonal)
   double* Rout = sweep == 1 ? a.R1 : a.R2;
   double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
-  for (int i = tid; i < K * K; i += NT) {
-    const int r = i / K, c = i % K;
-    gst(&Rout[i], c >= r ? L[r * LDL + c] : 0.0);
-  }
+  for (int r = wave; r < K; r += NT / 64)
+    for (int c = lane; c < K; c += 64) {
+      const double lv = L[r * LDL + c];
+      gst(&Rout[r * K + c], lv * (c >= r ? 1.0 : 0.0));
+    }
   __syncthreads();   // the lower blocks of L are overwritten below
 
   // ---- X = R^{-1} by blocked back substitution; X_pq (p < q) is kept
@@ -219,14 +238,12 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     }
     __syncthreads();
   }
-  for (int i = tid; i < K * K; i += NT) {
-    const int r = i / K, c = i % K;
-    const int pr = r >> 4, pc = c >> 4;
-    double v = 0.0;
-    if (pr == pc) v = Xd[pr][(r & 15) * LDD + (c & 15)];
-    else if (pr < pc) v = L[c * LDL + r];
-    gst(&Riout[i], v);
-  }
+  for (int r = wave; r < K; r += NT / 64)
+    for (int c = lane; c < K; c += 64) {
+      const int pr = r >> 4, pc = c >> 4;
+      const double xd = Xd[pr][(r & 15) * LDD + (c & 15)], lv = L[c * LDL + r];
+      gst(&Riout[r * K + c], xd * (pr == pc ? 1.0 : 0.0) + lv * (pr < pc ? 1.0 : 0.0));
+    }
   if (sweep == 2 && any && tid == 0) atomicOr(&st->flags, 1u);
 }
 

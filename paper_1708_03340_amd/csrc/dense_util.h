@@ -49,6 +49,13 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
+// Value of v in lane src (src uniform).
+__device__ __forceinline__ double lane_val(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // DPP move of a double within rows of 16 lanes (CTRL: a DPP control code).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {

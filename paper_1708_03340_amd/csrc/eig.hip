@@ -37,13 +37,6 @@ __device__ __forceinline__ double rsqrt3(double x) {
   return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-// Value of v in lane src (src uniform).
-__device__ __forceinline__ double lane_val(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
 // Sum over a wave of 64 lanes, returned to every lane: DPP sums in rows of
 // 16, then the four row sums.
 __device__ __forceinline__ double wave_sum(double v) {

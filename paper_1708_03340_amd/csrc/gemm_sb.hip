@@ -34,10 +34,11 @@ __device__ __forceinline__ double ld_as_double(const char* p) {
   return (double)gld(reinterpret_cast<const T*>(p));
 }
 
-template <typename TS, typename TT, int WN>
+template <typename TS, typename TT, int WN, int CD>
 __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __restrict__ descs, int swap,
                                                              int tC) {
   constexpr int SB_NT = 512 / WN;     // 8 / WN waves, each 16 * WN columns of a 128-column tile
+  constexpr int KS = CD / 4;          // 4-deep MFMA steps per chunk (CD = chunk depth, 32 or 64)
   __shared__ double Ss[SB_K][SB_MP];
   __shared__ const char* trow[SB_K];   // byte address of T[k][0] (batch 0)
   __shared__ const char* srow[SB_K];   // byte address of S[0][k] (batch 0)
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
       trow[tid] = Aseg + kl * sAk * esT;
     }
   }
-  const int Kp = (Kt + 31) & ~31;          // reduction padded to whole 32-deep chunks
-  const int nchunk = Kp >> 5;
+  const int Kp = (Kt + CD - 1) / CD * CD;  // reduction padded to whole chunks
+  const int nchunk = Kp / CD;
   const int tilesN = (Ns + SB_TN - 1) / SB_TN;
   const int nitems = tilesN * D.nbatch;
   double alpha = D.alpha;
@@ -96,8 +97,8 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
     __syncthreads();
   };
 
-  // T operand of chunk c of item it: b[kk][j] = T[32c + 4kk + lane/16][n0 + 16 WN wave + 16j + lane%16]
-  auto load_T = [&](int it, int c, double (&bf)[8][WN]) {
+  // T operand of chunk c of item it: b[kk][j] = T[CD c + 4kk + lane/16][n0 + 16 WN wave + 16j + lane%16]
+  auto load_T = [&](int it, int c, double (&bf)[KS][WN]) {
     const int b = it / tilesN, tn = it % tilesN;
     const int64_t boff = (int64_t)b * t_b;
 #pragma unroll
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
       const int n = min(tn * SB_TN + wave * 16 * WN + 16 * j + (lane & 15), Ns - 1);
       const int64_t noff = boff + n * t_n;
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) bf[kk][j] = ld_as_double<TT>(trow[(c << 5) + 4 * kk + (lane >> 4)] + noff);
+      for (int kk = 0; kk < KS; ++kk) bf[kk][j] = ld_as_double<TT>(trow[c * CD + 4 * kk + (lane >> 4)] + noff);
     }
   };
 
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
   int cur_b = it / tilesN;
   __syncthreads();   // row tables visible
   load_S(cur_b);
-  double bc[8][WN], bn[8][WN];
+  double bc[KS][WN], bn[KS][WN];
   load_T(it, 0, bc);
   while (true) {
     const int next = it + gridDim.x;
@@ -129,8 +130,8 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
       if (more_here) load_T(it, c + 1, bn);
       else if (next < nitems) load_T(next, 0, bn);
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = (c << 5) + 4 * kk + (lane >> 4);
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = c * CD + 4 * kk + (lane >> 4);
         double a[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = Ss[k][16 * i + (lane & 15)];
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bc[kk][j], acc[i][j], 0, 0, 0);
       }
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk)
+      for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
         for (int j = 0; j < WN; ++j) bc[kk][j] = bn[kk][j];
     }
@@ -179,10 +180,10 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
 template <typename TS, typename TT>
 hipError_t go_sb(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.sb_grid, g.ndesc, 1);
-  if (g.sb_wn == 2)
-    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 2>), grid, dim3(256), 0, s, g.descs, g.sb_swap, g.tC);
+  if (g.sb_cd == 64)
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 64>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
   else
-    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 32>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
   return hipGetLastError();
 }
 
