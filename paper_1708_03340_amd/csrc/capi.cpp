@@ -1219,13 +1219,11 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
     }
     g_label = "gramian_mode1";
     add_gemm(P, dc, F64, tq, F64, MATH_F64, GEMM_STORE, true, false);
-    // the son Gramians are symmetric because Bhat_t is (only the first one
-    // uses it: for the second, with row-contiguous operands, the 64 x 64
-    // tiles are faster)
+    // the son Gramians are symmetric because Bhat_t is
     g_label = "gramian_son1";
     add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true, false, 4096, true);
     g_label = "gramian_son2";
-    add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false);
+    add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false, false, 4096, true);
   }
 }
 

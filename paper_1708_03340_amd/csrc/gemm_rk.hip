@@ -14,8 +14,8 @@
 // and B permuted alike.  When the result is symmetric (a Gram matrix, B = A^T
 // of the same matrix, or a son Gramian, which inherits the symmetry of
 // Bhat_t) only the 36 blocks of 16 x 16 on or above the diagonal are formed,
-// each wave taking block rows w and 7-w, and the off-diagonal blocks are
-// added at both places.
+// each wave taking the nine blocks of block rows w and 7-w, and the
+// off-diagonal blocks are added at both places.
 #include "ht_internal.h"
 
 namespace ht {
@@ -45,7 +45,7 @@ template <> struct RkTraits<float> {
 // MODE 0: full result; 1: Gram matrix (B = A^T, upper blocks); 2: separate B
 // but a symmetric result (upper blocks, mirrored), as for the son Gramians
 template <typename TA, typename TB, typename TM, int MODE, int RK_KC>
-__global__ __launch_bounds__(RK_NT, MODE == 1 ? 2 : 1) void gemm_rk_kernel(const GemmDesc* __restrict__ descs,
+__global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const GemmDesc* __restrict__ descs,
                                                                         int nsplit, int tC, int mode) {
   constexpr bool SYM = MODE != 0;      // upper blocks only
   constexpr bool SAMEB = MODE == 1;    // B fragments read from A
@@ -111,93 +111,194 @@ __global__ __launch_bounds__(RK_NT, MODE == 1 ? 2 : 1) void gemm_rk_kernel(const
     }
   };
 
-  // blocks of this wave: FULL: rows 4(w/2) + i, columns 4(w%2) + j;
-  // SYM: block rows w and 7-w against block columns on or right of them
-  constexpr int NA = SYM ? 2 : 4, NB = SYM ? 8 : 4;
-  V acc[NA][NB];
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = V{0, 0, 0, 0};
-  auto rowblk = [&](int i) { return SYM ? (i == 0 ? wave : 7 - wave) : 4 * (wave >> 1) + i; };
-  auto colblk = [&](int j) { return SYM ? j : 4 * (wave & 1) + j; };
+  // result writes (scale read after the reduction, in each epilogue)
+  auto put = [&](int m, int n, double val) {
+    const int64_t off = (int64_t)m * D.sCm + (int64_t)n * D.sCn;
+    if (tC == F64) {
+      double* p = reinterpret_cast<double*>(D.C) + off;
+      if (mode == GEMM_ATOMIC) gatomic_add(p, val); else gst(p, val);
+    } else {
+      float* p = reinterpret_cast<float*>(D.C) + off;
+      if (mode == GEMM_ATOMIC) gatomic_add(p, (float)val); else gst(p, (float)val);
+    }
+  };
+  auto scale = [&]() {
+    double alpha = D.alpha;
+    if (D.alpha_dev) alpha *= gld(D.alpha_dev);
+    return alpha;
+  };
 
   load(c0);
   stash(0);
   __syncthreads();
   int buf = 0;
-  for (int c = c0; c < c1; ++c) {
-    const bool more = c + 1 < c1;
-    if (more) load(c + 1);
-    // four consecutive k of the lane's row per 16-deep step, k = 16s + 4 (lane / 16) + q,
-    // read in two halves of two to keep the fragment registers few
+  if constexpr (SAMEB) {
+    // Gram matrix: block rows w and 7-w against the block columns right of
+    // them; the column fragments of one step are read once and serve both
+    // rows (the skipped blocks are uniform per wave)
+    V acc[2][8];
 #pragma unroll
-    for (int st = 0; st < RK_KC / 16; ++st) {
-      const int kq = 16 * st + 4 * (lane >> 4);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int hq = 0; hq < 2; ++hq) {
-        TM fa[NA][2], fb[NB][2];
+      for (int j = 0; j < 8; ++j) acc[i][j] = V{0, 0, 0, 0};
+    for (int c = c0; c < c1; ++c) {
+      const bool more = c + 1 < c1;
+      if (more) load(c + 1);
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          const TM* p = &As[buf][16 * rowblk(i) + (lane & 15)][kq + 2 * hq];
-          fa[i][0] = p[0];
-          fa[i][1] = p[1];
+      for (int st = 0; st < RK_KC / 16; ++st) {
+        const int kq = 16 * st + 4 * (lane >> 4);
+#pragma unroll
+        for (int hq = 0; hq < 2; ++hq) {
+          TM fa[2][2], fb[8][2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const TM* p = &As[buf][16 * (i == 0 ? wave : 7 - wave) + (lane & 15)][kq + 2 * hq];
+            fa[i][0] = p[0];
+            fa[i][1] = p[1];
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (j < wave) continue;   // block columns left of both rows
+            const TM* p = &As[buf][16 * j + (lane & 15)][kq + 2 * hq];
+            fb[j][0] = p[0];
+            fb[j][1] = p[1];
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                if (i == 1 && j < 4) continue;   // block row 7-w >= 4: never left of 4
+                if (j < (i == 0 ? wave : 7 - wave)) continue;
+                acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
+              }
         }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (SYM && j < wave) continue;   // block columns left of both rows
-          const TM* p = SAMEB ? &As[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq]
-                              : &Bs[buf][16 * colblk(j) + (lane & 15)][kq + 2 * hq];
-          fb[j][0] = p[0];
-          fb[j][1] = p[1];
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              if (SYM && i == 1 && j < 4) continue;   // block row 7-w >= 4: never left of 4
-              if (SYM && colblk(j) < rowblk(i)) continue;
-              acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
-            }
       }
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
-    if (more) stash(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-
-  double alpha = D.alpha;
-  if (D.alpha_dev) alpha *= gld(D.alpha_dev);
-  char* Cb = reinterpret_cast<char*>(D.C);
-  auto put = [&](int m, int n, double val) {
-    const int64_t off = (int64_t)m * D.sCm + (int64_t)n * D.sCn;
-    if (tC == F64) {
-      double* p = reinterpret_cast<double*>(Cb) + off;
-      if (mode == GEMM_ATOMIC) gatomic_add(p, val); else gst(p, val);
-    } else {
-      float* p = reinterpret_cast<float*>(Cb) + off;
-      if (mode == GEMM_ATOMIC) gatomic_add(p, (float)val); else gst(p, (float)val);
+    const double alpha = scale();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int rbk = i == 0 ? wave : 7 - wave;
+        if (i == 1 && j < 4) continue;
+        if (j < rbk) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rbk + Tr::row(v, lane), n = 16 * j + (lane & 15);
+          if (m < M && n < N) {
+            const double val = alpha * (double)acc[i][j][v];
+            put(m, n, val);
+            if (j != rbk) put(n, m, val);
+          }
+        }
+      }
+  } else if constexpr (SYM) {
+    // symmetric result of two operands: the wave's nine blocks, row block w
+    // against columns w..7, then row block 7-w against columns 7-w..7 (36
+    // upper blocks over four waves); exactly nine accumulators, so two
+    // workgroups fit a CU
+    const int nfirst = 8 - wave;
+    auto bcol = [&](int bl) { return bl < nfirst ? wave + bl : (7 - wave) + (bl - nfirst); };
+    V acc[9];
+#pragma unroll
+    for (int bl = 0; bl < 9; ++bl) acc[bl] = V{0, 0, 0, 0};
+    for (int c = c0; c < c1; ++c) {
+      const bool more = c + 1 < c1;
+      if (more) load(c + 1);
+#pragma unroll
+      for (int st = 0; st < RK_KC / 16; ++st) {
+        const int kq = 16 * st + 4 * (lane >> 4);
+#pragma unroll
+        for (int hq = 0; hq < 2; ++hq) {
+          const TM* pa0 = &As[buf][16 * wave + (lane & 15)][kq + 2 * hq];
+          const TM* pa1 = &As[buf][16 * (7 - wave) + (lane & 15)][kq + 2 * hq];
+          const TM fa0[2] = {pa0[0], pa0[1]}, fa1[2] = {pa1[0], pa1[1]};
+#pragma unroll
+          for (int bl = 0; bl < 9; ++bl) {
+            const int col = bcol(bl);
+            const TM* pb = SAMEB ? &As[buf][16 * col + (lane & 15)][kq + 2 * hq]
+                                 : &Bs[buf][16 * col + (lane & 15)][kq + 2 * hq];
+            const TM fb0 = pb[0], fb1 = pb[1];
+            const bool first = bl < nfirst;
+            acc[bl] = Tr::mfma(first ? fa0[0] : fa1[0], fb0, acc[bl]);
+            acc[bl] = Tr::mfma(first ? fa0[1] : fa1[1], fb1, acc[bl]);
+          }
+        }
+      }
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
-  };
+    const double alpha = scale();
 #pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int rbk = rowblk(i), cbk = colblk(j);
-      if (SYM && i == 1 && j < 4) continue;
-      if (SYM && cbk < rbk) continue;
+    for (int bl = 0; bl < 9; ++bl) {
+      const int rbk = bl < nfirst ? wave : 7 - wave, cbk = bcol(bl);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * rbk + Tr::row(v, lane), n = 16 * cbk + (lane & 15);
         if (m < M && n < N) {
-          const double val = alpha * (double)acc[i][j][v];
+          const double val = alpha * (double)acc[bl][v];
           put(m, n, val);
-          if (SYM && cbk != rbk) put(n, m, val);
+          if (cbk != rbk) put(n, m, val);
         }
       }
     }
+  } else {
+    // full result: wave w owns block rows 4(w/2) .. +3 and columns 4(w%2) .. +3
+    V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
+    for (int c = c0; c < c1; ++c) {
+      const bool more = c + 1 < c1;
+      if (more) load(c + 1);
+#pragma unroll
+      for (int st = 0; st < RK_KC / 16; ++st) {
+        const int kq = 16 * st + 4 * (lane >> 4);
+#pragma unroll
+        for (int hq = 0; hq < 2; ++hq) {
+          TM fa[4][2], fb[4][2];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const TM* p = &As[buf][16 * (4 * (wave >> 1) + i) + (lane & 15)][kq + 2 * hq];
+            fa[i][0] = p[0];
+            fa[i][1] = p[1];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const TM* p = &Bs[buf][16 * (4 * (wave & 1) + j) + (lane & 15)][kq + 2 * hq];
+            fb[j][0] = p[0];
+            fb[j][1] = p[1];
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
+        }
+      }
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    const double alpha = scale();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * (4 * (wave >> 1) + i) + Tr::row(v, lane), n = 16 * (4 * (wave & 1) + j) + (lane & 15);
+          if (m < M && n < N) put(m, n, alpha * (double)acc[i][j][v]);
+        }
+  }
 }
 
 template <typename TA, typename TB, typename TM>
