@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <list>
 #include <map>
 #include <mutex>
@@ -72,7 +73,9 @@ namespace {
 
 enum OpKind : int {
   OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
-  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_FINISHR
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_FINISHR,
+  OP_FORK,   // the library's second stream waits for the caller's stream here
+  OP_JOIN    // the caller's stream waits for everything on the second stream
 };
 
 struct Op {
@@ -96,10 +99,13 @@ struct Op {
   int tblocks = 4096;        // OP_GEMM: target workgroups of a split reduction
   bool sym_out = false;      // OP_GEMM: every result is symmetric
   bool acc64_req = false;    // OP_GEMM: float64 accumulation across k-slabs was asked for
+  int stream = 0;            // 0: the caller's stream; 1: the library's second stream
 };
 
 // Label given to the launches added next (one per step of the method).
 static thread_local const char* g_label = "";
+// Stream of the launches added next (0: the caller's, 1: the second stream).
+static thread_local int g_stream = 0;
 struct Label {
   const char* prev;
   explicit Label(const char* l) : prev(g_label) { g_label = l; }
@@ -265,6 +271,7 @@ void add_gemm(Plan& P, const std::vector<GemmDesc>& descs, int tA, int tB, int t
   if (descs.empty()) return;
   Op op = gemm_op(descs, tA, tB, tC, math, mode, akc, bkc, acc64, target_blocks, sym_out);
   op.toff = put(P, descs);
+  op.stream = g_stream;
   P.ops.push_back(op);
 }
 
@@ -273,9 +280,19 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
   Op op;
   op.kind = kind;
   op.label = g_label;
-  for (const auto& x : a) op.bytes_alg += 2.0 * 8.0 * x.K * x.K;
+  for (const auto& x : a) {
+    op.i0 = std::max(op.i0, (int)x.K);   // the largest order (OP_EIG picks its kernel by it)
+    op.bytes_alg += 2.0 * 8.0 * x.K * x.K;
+    const double k3 = (double)x.K * x.K * x.K;
+    // operation counts: symmetric eigensolver with vectors (Householder
+    // tridiagonalisation 4/3 K^3, implicit QL with vectors about 6 K^3,
+    // back-transformation 2 K^3); Cholesky K^3/3 and triangular inverse K^3/3
+    if (kind == OP_EIG) op.flops += (4.0 / 3.0 + 8.0) * k3;
+    if (kind == OP_CHOL1 || kind == OP_CHOL2) op.flops += 2.0 / 3.0 * k3;
+  }
   op.toff = put(P, a);
   op.count = (int)a.size();
+  op.stream = g_stream;
   P.ops.push_back(op);
 }
 
@@ -284,6 +301,7 @@ void add_fills(Plan& P, const std::vector<FillRec>& r) {
   for (const auto& f : r) mx = std::max(mx, f.bytes);
   if (!mx) return;
   Op op; op.kind = OP_FILL; op.toff = put(P, r); op.count = (int)r.size(); op.bytes = mx; op.label = g_label;
+  op.stream = g_stream;
   for (const auto& f : r) op.bytes_alg += (double)f.bytes;
   P.ops.push_back(op);
 }
@@ -298,6 +316,7 @@ void add_copies(Plan& P, const std::vector<CopyRec>& r) {
   for (const auto& c : r) mx = std::max<int64_t>(mx, c.n0 * c.n1 * c.n2);
   if (mx <= 0) return;
   Op op; op.kind = OP_COPY; op.toff = put(P, r); op.count = (int)r.size(); op.c[0] = mx; op.label = g_label;
+  op.stream = g_stream;
   for (const auto& c : r) op.bytes_alg += (double)(c.n0 * c.n1 * c.n2) * (esize(c.tsrc) + esize(c.tdst));
   P.ops.push_back(op);
 }
@@ -328,6 +347,13 @@ StateRec blank_state(GlobalState* st) {
 void add_state(Plan& P, int kind, const std::vector<StateRec>& r) {
   if (r.empty()) return;
   Op op; op.kind = kind; op.toff = put(P, r); op.count = (int)r.size(); op.label = g_label;
+  op.stream = g_stream;
+  P.ops.push_back(op);
+}
+
+// Fork to or join from the second stream.
+void add_sync(Plan& P, int kind) {
+  Op op; op.kind = kind; op.label = kind == OP_FORK ? "fork" : "join";
   P.ops.push_back(op);
 }
 
@@ -362,6 +388,7 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
       }
       Op op = decide(chunk);
       op.label = proto.label;
+      op.stream = proto.stream;
       op.toff = put(P, chunk);
       P.ops.push_back(op);
     }
@@ -467,6 +494,26 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           op.flops += b.flops;
           op.bytes_alg += b.bytes_alg;
         }
+        if (o0.kind == OP_EIG) {
+          // the eigensolver by order: nodes up to 64 run two to a CU
+          std::vector<SmallArgs> lo, hi;
+          for (const auto& x : sa) (x.K <= 64 ? lo : hi).push_back(x);
+          for (const auto* part : {&lo, &hi}) {
+            if (part->empty()) continue;
+            Op e = op;
+            e.toff = put(M, *part);
+            e.count = (int)part->size();
+            e.i0 = 0;
+            e.flops = e.bytes_alg = 0.0;
+            for (const auto& x : *part) {
+              e.i0 = std::max(e.i0, (int)x.K);
+              e.bytes_alg += 2.0 * 8.0 * x.K * x.K;
+              e.flops += (4.0 / 3.0 + 8.0) * (double)x.K * x.K * x.K;
+            }
+            M.ops.push_back(e);
+          }
+          break;
+        }
         op.toff = put(M, sa);
         op.count = (int)sa.size();
         if (o0.kind == OP_RANK) {
@@ -476,6 +523,9 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
         M.ops.push_back(op);
         break;
       }
+      case OP_FORK: case OP_JOIN:
+        add_sync(M, o0.kind);
+        break;
       case OP_FILL: {
         std::vector<FillRec> r;
         for (const auto& pr : grp) {
@@ -483,9 +533,12 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           r.insert(r.end(), src, src + pr.second->count);
         }
         const char* l = g_label;
+        const int sm = g_stream;
         g_label = o0.label;
+        g_stream = o0.stream;
         add_fills(M, r);
         g_label = l;
+        g_stream = sm;
         break;
       }
       case OP_COPY: {
@@ -495,9 +548,12 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           r.insert(r.end(), src, src + pr.second->count);
         }
         const char* l = g_label;
+        const int sm = g_stream;
         g_label = o0.label;
+        g_stream = o0.stream;
         add_copies(M, r);
         g_label = l;
+        g_stream = sm;
         break;
       }
       case OP_SETSTATE: case OP_ROOTNORM: case OP_WRITESCALE: {
@@ -507,9 +563,12 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           r.insert(r.end(), src, src + pr.second->count);
         }
         const char* l = g_label;
+        const int sm = g_stream;
         g_label = o0.label;
+        g_stream = o0.stream;
         add_state(M, o0.kind, r);
         g_label = l;
+        g_stream = sm;
         break;
       }
       default:
@@ -536,6 +595,9 @@ struct ProfAgg { std::string label, kernel; long long n = 0; double ms = 0, flop
 struct ht_context {
   int device = 0;
   std::mutex mu;
+  std::mutex run_mu;                     // one plan at a time uses the second stream
+  hipStream_t side = nullptr;            // second stream (default priority), created on first use
+  std::vector<hipEvent_t> sync_events;   // fork / join events
   std::list<Plan> cache;   // most recent first
   bool prof = false;
   std::vector<hipEvent_t> free_events;
@@ -586,7 +648,29 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
     }
   }
   char* tb = reinterpret_cast<char*>(dtable);
+  bool forks = false;
+  for (const auto& op : P.ops) forks = forks || op.kind == OP_FORK;
+  std::unique_lock<std::mutex> run_lk;
+  if (forks) {
+    run_lk = std::unique_lock<std::mutex>(ctx->run_mu);
+    if (!ctx->side) HT_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  }
+  size_t nsync = 0;
   for (auto& op : P.ops) {
+    if (op.kind == OP_FORK || op.kind == OP_JOIN) {
+      if (nsync == ctx->sync_events.size()) {
+        hipEvent_t ev = nullptr;
+        HT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ctx->sync_events.push_back(ev);
+      }
+      hipEvent_t ev = ctx->sync_events[nsync++];
+      hipStream_t from = op.kind == OP_FORK ? stream : ctx->side, to = op.kind == OP_FORK ? ctx->side : stream;
+      HT_HIP(hipEventRecord(ev, from));
+      HT_HIP(hipStreamWaitEvent(to, ev, 0));
+      continue;
+    }
+    const hipStream_t ostream = stream;
+    if (op.stream) stream = ctx->side;
     hipError_t e = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->prof) {
@@ -611,7 +695,7 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
                             reinterpret_cast<GlobalState*>(op.p0));
         break;
       case OP_EIG:
-        e = launch_eig(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, nullptr, stream,
+        e = launch_eig(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, op.i0, stream,
                        reinterpret_cast<GlobalState*>(op.p0));
         break;
       case OP_RANK:
@@ -659,6 +743,7 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
       const std::string kn = kernel_name(op);
       ctx->pending.push_back({ev0, ev1, (op.label && *op.label) ? op.label : "other", kn, op.flops, op.bytes_alg});
     }
+    stream = ostream;
   }
   return HT_OK;
 }
@@ -684,7 +769,7 @@ std::string kernel_name(const Op& op) {
              (op.g.math == MATH_F32 && op.g.acc64 ? "true" : "false") + ">";
     case OP_CHOL1: case OP_CHOL2: return "chol_kernel";
     case OP_FINISHR: return "finish_r_kernel";
-    case OP_EIG: return "eig_kernel";
+    case OP_EIG: return op.i0 <= 64 ? "eig_kernel<64>" : "eig_kernel<128>";
     case OP_RANK: return "rank_kernel";
     case OP_PROJPREP: return "proj_prep_kernel";
     case OP_SIGMA: return "sigma_kernel";
@@ -696,6 +781,8 @@ std::string kernel_name(const Op& op) {
     case OP_EGATHER: return "gather_kernel";
     case OP_ENORM: return "normalize_kernel";
     case OP_EFINISH: return "finish_kernel";
+    case OP_FORK: return "fork";
+    case OP_JOIN: return "join";
   }
   return "?";
 }
@@ -1161,8 +1248,11 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
 
 // Top-down Gramians (eqs. (acctransferroot), (acctransferSon1/2)) from the
 // orthogonal root BDo and orthogonal transfer tensors Qo[t] (type tq).
+// after(dep), if given, is called once the Gramians of all nodes down to
+// depth dep + 1 are planned.
 void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vector<NodeBufs>& nb,
-                   const double* BDo, GlobalState* st, const std::vector<const void*>& Qo, int tq) {
+                   const double* BDo, GlobalState* st, const std::vector<const void*>& Qo, int tq,
+                   const std::function<void(int)>& after = nullptr) {
   const int t1 = tr.son1[0], t2 = tr.son2[0];
   const int K1r = K[t1], K2r = K[t2];
   g_label = "gramian_root";
@@ -1188,6 +1278,7 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
     b.push_back(h);
     add_gemm(P, b, F64, F64, F64, MATH_F64, GEMM_STORE, false, false);
   }
+  if (after) after(0);
   const int D = tr.max_depth();
   for (int dep = 1; dep < D; ++dep) {
     std::vector<GemmDesc> dc, ds1, ds2;
@@ -1224,6 +1315,7 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
     add_gemm(P, ds1, tq, F64, F64, MATH_F64, GEMM_ATOMIC, true, true, false, 4096, true);
     g_label = "gramian_son2";
     add_gemm(P, ds2, tq, F64, F64, MATH_F64, GEMM_ATOMIC, false, false, false, 4096, true);
+    if (after) after(dep);
   }
 }
 
@@ -1265,6 +1357,8 @@ void ht_destroy_context(ht_context* ctx) {
   for (auto& p : ctx->cache) (void)hipFree(p.dtable);
   for (auto& p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto& e : ctx->free_events) (void)hipEventDestroy(e);
+  for (auto& e : ctx->sync_events) (void)hipEventDestroy(e);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
 }
 
@@ -1285,10 +1379,12 @@ ht_status ht_tree(int32_t d, int32_t* parent, int32_t* son1, int32_t* son2, int3
 }
 
 // ------------------------------------------------------------------ truncation
+// overlap: run the upper part of the tree on the library's second stream
+// (see below); off for the plans of a batch, which are merged instead.
 static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
                                 const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
                                 int64_t* out_scale, uint32_t* flags, double* out_sigma, void* ws,
-                                Plan& P, size_t* need) {
+                                Plan& P, size_t* need, bool overlap = true) {
   (void)ctx;
   if (!opts) return fail(HT_EINVAL, "opts is NULL");
   if (opts->mode != HT_RANK_FIXED && opts->mode != HT_RANK_TOL) return fail(HT_EINVAL, "bad rank mode");
@@ -1335,43 +1431,69 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
   plan_orth(P, tr, S, prec, A, O, rcap, true, out, nullptr);
   std::vector<const void*> Qo(nn, nullptr);
   for (int t = 1; t < nn; ++t) Qo[t] = O.nb[t].Qo;
-  plan_gramians(P, tr, S.K, O.nb, O.BDo, O.st, Qo, T);
-  // eigen-decompositions of all Gramians, ranks, masked eigenvectors
-  std::vector<int> nonroot;
-  for (int t = 1; t < nn; ++t) nonroot.push_back(t);
-  std::vector<SmallArgs> sa;
-  for (int t : nonroot) {
-    NodeBufs& b = O.nb[t];
-    SmallArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.K = b.K; a.node = t; a.rcap = b.rcap; a.rfix = opts->mode == HT_RANK_FIXED ? rcap[t] : 0;
-    a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rf_type = T;
-    a.rank_dev = out_ranks ? out_ranks + t : b.rank;
-    a.scratch = b.scratch; a.Bh = b.Bh;
-    a.sigma_out = out_sigma ? out_sigma + (size_t)t * KMAX : nullptr;
-    a.st = O.st;
-    sa.push_back(a);
+  // Node groups.  An eigensolver launch lasts as long as one node's
+  // decomposition, whatever the number of nodes.  With overlap, the upper
+  // group (every non-root node above the deepest level) is decomposed on the
+  // second stream as soon as its Gramians exist, and the projections that
+  // need upper eigenvectors only (the root, inner nodes with upper sons,
+  // upper leaves) follow it there, while the caller's stream forms the last
+  // Gramian level and decomposes the lower group.  The rank rule of the
+  // lower group reuses the threshold the upper group computed (the sons of
+  // the root, which give ||A||, are upper).
+  const int Dmax = tr.max_depth();
+  const bool split = overlap && Dmax >= 2;
+  std::vector<char> upper(nn, 0);
+  std::vector<int> up_nodes, low_nodes;
+  for (int t = 1; t < nn; ++t) {
+    upper[t] = split && tr.depth[t] <= Dmax - 1;
+    (upper[t] ? up_nodes : low_nodes).push_back(t);
   }
-  g_label = "eig";
-  add_small(P, OP_EIG, sa);
-  P.ops.back().p0 = O.st;
-  g_label = "rank_select";
-  add_small(P, OP_RANK, sa);
-  {
-    StateRec r = blank_state(O.st);
-    r.a0 = 0; r.na = (int)sa.size(); r.d = d; r.mode = opts->mode; r.eps = opts->eps;
-    r.rel = opts->eps_relative ? 1 : 0; r.t1 = tr.son1[0]; r.t2 = tr.son2[0];
-    Op& op = P.ops.back();
-    op.toff2 = put(P, std::vector<StateRec>{r});
-    op.count2 = 1;
-  }
-  g_label = "proj_prep";
-  add_small(P, OP_PROJPREP, sa);
-  P.ops.back().p0 = O.st;
+  auto node_args = [&](const std::vector<int>& nodes) {
+    std::vector<SmallArgs> sa;
+    for (int t : nodes) {
+      NodeBufs& b = O.nb[t];
+      SmallArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.K = b.K; a.node = t; a.rcap = b.rcap; a.rfix = opts->mode == HT_RANK_FIXED ? rcap[t] : 0;
+      a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rf_type = T;
+      a.rank_dev = out_ranks ? out_ranks + t : b.rank;
+      a.scratch = b.scratch; a.Bh = b.Bh;
+      a.sigma_out = out_sigma ? out_sigma + (size_t)t * KMAX : nullptr;
+      a.st = O.st;
+      sa.push_back(a);
+    }
+    return sa;
+  };
+  auto emit_eig = [&](const std::vector<int>& nodes, const char* label) {
+    if (nodes.empty()) return;
+    g_label = label;
+    add_small(P, OP_EIG, node_args(nodes));
+    P.ops.back().p0 = O.st;
+  };
+  auto emit_rank_prep = [&](const std::vector<int>& nodes, const char* l_rank, const char* l_prep) {
+    if (nodes.empty()) return;
+    const std::vector<SmallArgs> sa = node_args(nodes);
+    g_label = l_rank;
+    add_small(P, OP_RANK, sa);
+    {
+      StateRec r = blank_state(O.st);
+      r.a0 = 0; r.na = (int)sa.size(); r.d = d; r.mode = opts->mode; r.eps = opts->eps;
+      r.rel = opts->eps_relative ? 1 : 0; r.t1 = tr.son1[0]; r.t2 = tr.son2[0];
+      Op& op = P.ops.back();
+      op.toff2 = put(P, std::vector<StateRec>{r});
+      op.count2 = 1;
+    }
+    g_label = l_prep;
+    add_small(P, OP_PROJPREP, sa);
+    P.ops.back().p0 = O.st;
+  };
   // projections (eq. (nodewisetruncation), eq. (transfertransformationtrunc), root rule)
-  {
+  // of the given leaves (by mode), inner nodes and, if root, the root
+  struct ProjLabels { const char *factor, *leaf, *m1, *m2, *m3, *root; };
+  auto emit_proj = [&](const std::vector<int>& modes, const std::vector<int>& inner, bool root,
+                       const ProjLabels& L) {
     std::vector<GemmDesc> dp, du, d1, d2, d3;
-    for (int mu = 0; mu < d; ++mu) {
+    for (int mu : modes) {
       const int t = tr.leaf_node[mu];
       NodeBufs& b = O.nb[t];
       GemmDesc g = blank_desc();  // Pm = R^{-1} Qm
@@ -1394,8 +1516,7 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
       u.M = (int)X[0].n[mu]; u.N = b.rcap;
       du.push_back(u);
     }
-    for (int t = 1; t < nn; ++t) {
-      if (tr.is_leaf(t)) continue;
+    for (int t : inner) {
       NodeBufs& b = O.nb[t];
       const int s1 = tr.son1[t], s2 = tr.son2[t];
       const int K1 = S.K[s1], K2 = S.K[s2];
@@ -1419,36 +1540,64 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
       q.M = b.rcap * O.nb[s1].rcap; q.N = O.nb[s2].rcap; q.K = K2;
       d3.push_back(q);
     }
-    g_label = "proj_leaf_factor";
+    g_label = L.factor;
     add_gemm(P, dp, F64, F64, T, MATH_F64, GEMM_STORE, true, false);
-    g_label = "proj_leaf";
+    g_label = L.leaf;
     add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false, true);
-    g_label = "proj_inner_mode1";
+    g_label = L.m1;
     add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false, true);
-    g_label = "proj_inner_mode2";
+    g_label = L.m2;
     add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
-    g_label = "proj_inner_mode3";
+    g_label = L.m3;
     add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true, true);
-    g_label = "proj_root";
-    // root: Qm_t1^T BDo Qm_t2
-    const int t1 = tr.son1[0], t2 = tr.son2[0];
-    const int K1r = S.K[t1], K2r = S.K[t2];
-    std::vector<GemmDesc> r1, r2;
-    GemmDesc g = blank_desc();
-    g.A = O.nb[t1].Qm; g.sAm = 1; g.sAk = O.nb[t1].rcap;
-    g.B = O.BDo; g.sBk = K2r; g.sBn = 1;
-    g.C = O.T1; g.sCm = K2r; g.sCn = 1;
-    g.M = O.nb[t1].rcap; g.N = K2r; g.K = K1r;
-    r1.push_back(g);
-    add_gemm(P, r1, F64, F64, F64, MATH_F64, GEMM_STORE, false, false);
-    GemmDesc h = blank_desc();
-    h.A = O.T1; h.sAm = K2r; h.sAk = 1;
-    h.B = O.nb[t2].Qm; h.sBk = O.nb[t2].rcap; h.sBn = 1;
-    h.C = need ? nullptr : out->transfer[0]; h.sCm = O.nb[t2].rcap; h.sCn = 1;
-    h.M = O.nb[t1].rcap; h.N = O.nb[t2].rcap; h.K = K2r;
-    r2.push_back(h);
-    add_gemm(P, r2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    if (root) {
+      g_label = L.root;
+      // root: Qm_t1^T BDo Qm_t2
+      const int t1 = tr.son1[0], t2 = tr.son2[0];
+      const int K1r = S.K[t1], K2r = S.K[t2];
+      std::vector<GemmDesc> r1, r2;
+      GemmDesc g = blank_desc();
+      g.A = O.nb[t1].Qm; g.sAm = 1; g.sAk = O.nb[t1].rcap;
+      g.B = O.BDo; g.sBk = K2r; g.sBn = 1;
+      g.C = O.T1; g.sCm = K2r; g.sCn = 1;
+      g.M = O.nb[t1].rcap; g.N = K2r; g.K = K1r;
+      r1.push_back(g);
+      add_gemm(P, r1, F64, F64, F64, MATH_F64, GEMM_STORE, false, false);
+      GemmDesc h = blank_desc();
+      h.A = O.T1; h.sAm = K2r; h.sAk = 1;
+      h.B = O.nb[t2].Qm; h.sBk = O.nb[t2].rcap; h.sBn = 1;
+      h.C = need ? nullptr : out->transfer[0]; h.sCm = O.nb[t2].rcap; h.sCn = 1;
+      h.M = O.nb[t1].rcap; h.N = O.nb[t2].rcap; h.K = K2r;
+      r2.push_back(h);
+      add_gemm(P, r2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    }
+  };
+  // which projections can run with the upper eigenvectors alone
+  std::vector<int> modes_up, modes_low, inner_up, inner_low;
+  for (int mu = 0; mu < d; ++mu) (upper[tr.leaf_node[mu]] ? modes_up : modes_low).push_back(mu);
+  for (int t = 1; t < nn; ++t) {
+    if (tr.is_leaf(t)) continue;
+    (upper[tr.son1[t]] && upper[tr.son2[t]] ? inner_up : inner_low).push_back(t);
   }
+  const bool root_up = upper[tr.son1[0]] && upper[tr.son2[0]];
+  const ProjLabels lab_low{"proj_leaf_factor", "proj_leaf", "proj_inner_mode1", "proj_inner_mode2",
+                           "proj_inner_mode3", "proj_root"};
+  const ProjLabels lab_up{"proj_leaf_factor_upper", "proj_leaf_upper", "proj_inner_mode1_upper",
+                          "proj_inner_mode2_upper", "proj_inner_mode3_upper", "proj_root_upper"};
+  auto upper_part = [&](int dep) {
+    if (!split || dep != Dmax - 2) return;
+    add_sync(P, OP_FORK);
+    g_stream = 1;
+    emit_eig(up_nodes, "eig_upper");
+    emit_rank_prep(up_nodes, "rank_select_upper", "proj_prep_upper");
+    emit_proj(modes_up, inner_up, root_up, lab_up);
+    g_stream = 0;
+  };
+  plan_gramians(P, tr, S.K, O.nb, O.BDo, O.st, Qo, T, upper_part);
+  emit_eig(low_nodes, "eig");
+  if (split) add_sync(P, OP_JOIN);
+  emit_rank_prep(low_nodes, "rank_select", "proj_prep");
+  emit_proj(modes_low, inner_low, !root_up, lab_low);
   {
     g_label = "finish";
     StateRec r = blank_state(O.st);
@@ -1530,7 +1679,7 @@ static ht_status build_truncate_batched(ht_context* ctx, int32_t count, const ht
       char* wc = reinterpret_cast<char*>(ws) + off;
       st = build_truncate(ctx, Xc, coef ? coef + first : nullptr, n_in[c], &opts[c], &out[c],
                           out_ranks ? out_ranks[c] : nullptr, out_scale + c, flags ? flags + c : nullptr,
-                          out_sigma ? out_sigma[c] : nullptr, wc, plans[c], nullptr);
+                          out_sigma ? out_sigma[c] : nullptr, wc, plans[c], nullptr, false);
       if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
     }
     off += nc;
@@ -2089,7 +2238,15 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
   g_rindex = RegionIndex();   // the regions are complete now: index them afresh
   auto at = [&](size_t off) { return P.table.data() + off; };
   int opi = 0;
+  bool forked = false;   // second-stream launches only between a fork and its join
   for (const auto& op : P.ops) {
+    if (op.kind == OP_FORK || op.kind == OP_JOIN) {
+      if (forked != (op.kind == OP_JOIN)) return fail(HT_EINVAL, "validator: unbalanced fork / join");
+      forked = op.kind == OP_FORK;
+      ++opi;
+      continue;
+    }
+    if (op.stream && !forked) return fail(HT_EINVAL, "validator: second-stream launch outside a fork");
     const std::string tag = "op " + std::to_string(opi++) + " kind " + std::to_string(op.kind);
     ht_status s = HT_OK;
     if (op.kind == OP_GEMM) {
@@ -2236,6 +2393,7 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
       }
     }
   }
+  if (forked) return fail(HT_EINVAL, "validator: plan ends with the second stream not joined");
   (void)m_entries;
   return HT_OK;
 }

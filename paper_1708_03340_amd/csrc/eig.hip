@@ -46,14 +46,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 enum : int { SWEEP_NONE = 0, SWEEP_ROT = 1, SWEEP_DONE = 2 };
 
-__global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
-  __shared__ double L[KMAX * (KMAX + 1)];       // Z during the QL phase
-  __shared__ double dg[KMAX], eo[KMAX];
-  __shared__ double rcs[2][KMAX], rss[2][KMAX];  // rotations of two sweeps
+// KT: the largest order the instantiation takes (64 or 128).  At KT = 64 the
+// LDS of a node is a quarter of that at 128 and two nodes share a CU (the
+// registers of the rotation blocks keep it from four).
+template <int KT>
+__global__ __launch_bounds__(NT, KT == 64 ? 2 : 1) void eig_kernel(const SmallArgs* __restrict__ args,
+                                                                   GlobalState* st) {
+  constexpr int RB = KT / 16;                    // row (column) blocks of 16
+  __shared__ double L[KT * (KT + 1)];            // Z during the QL phase
+  __shared__ double dg[KT], eo[KT];
+  __shared__ double rcs[2][KT], rss[2][KT];      // rotations of two sweeps
   __shared__ int sw_state[2], sw_m[2], sw_lo[2];
-  __shared__ double xs[KMAX], ps[KMAX];
+  __shared__ double xs[KT], ps[KT];
   __shared__ double part[16];
-  __shared__ int rankpos[KMAX];
+  __shared__ int rankpos[KT];
   __shared__ int sh_iters;
   const SmallArgs& a = args[blockIdx.x];
   if (a.st) st = a.st;
@@ -65,11 +71,11 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
 
   // ---- 1. tridiagonalisation, A in registers
   {
-    double A[8][8];
+    double A[RB][RB];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < RB; ++q) {
         const int r = ty + 16 * i, c = tx + 16 * q;
         A[i][q] = (r < K && c < K) ? gld(&a.Bh[r * K + c]) : 0.0;
       }
@@ -78,10 +84,10 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
       // publish column k below the diagonal, and the diagonal entry
       if (tx == (k & 15)) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < RB; ++q)
           if (q == kb) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < RB; ++i) {
               const int r = ty + 16 * i;
               xs[r] = r > k ? A[i][q] : 0.0;
               if (r == k) dg[k] = A[i][q];
@@ -91,7 +97,8 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
       __syncthreads();
       // every wave forms ||x||^2 itself (the same sum in the same order)
       const double x0 = xs[k + 1];
-      const double nrm2 = wave_sum(xs[lane] * xs[lane] + xs[lane + 64] * xs[lane + 64]);
+      const double nrm2 = KT > 64 ? wave_sum(xs[lane] * xs[lane] + xs[lane + 64] * xs[lane + 64])
+                                  : wave_sum(xs[lane] * xs[lane]);
       double tau = 0.0, alpha = x0;
       if (nrm2 > 0.0) {
         alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
@@ -101,56 +108,56 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
       if (tid > k && tid < K) gst(&Vs[k * K + tid - k - 1], tid == k + 1 ? x0 - alpha : xs[tid]);
       if (tau != 0.0) {
         // v (zero at indices <= k) at this thread's rows and columns
-        double vr[8], vc[8];
+        double vr[RB], vc[RB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < RB; ++i) {
           const int r = ty + 16 * i, c = tx + 16 * i;
           vr[i] = r == k + 1 ? x0 - alpha : xs[r];
           vc[i] = c == k + 1 ? x0 - alpha : xs[c];
         }
         // p = tau A v at this thread's rows, summed over the 16 lanes of the row group
-        double pr[8];
+        double pr[RB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < RB; ++i) {
           double s = 0.0;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) s = fma(A[i][q], vc[q], s);
+          for (int q = 0; q < RB; ++q) s = fma(A[i][q], vc[q], s);
           pr[i] = tau * row16_sum(s);
         }
         // v . p: partial over the 8 rows of the group, joined across groups in LDS
         double vp = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) vp = fma(vr[i], pr[i], vp);
+        for (int i = 0; i < RB; ++i) vp = fma(vr[i], pr[i], vp);
         if (tx == 0) {
           part[ty] = vp;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) ps[ty + 16 * i] = pr[i];
+          for (int i = 0; i < RB; ++i) ps[ty + 16 * i] = pr[i];
         }
         __syncthreads();
         double tot = 0.0;
 #pragma unroll
         for (int g = 0; g < 16; ++g) tot += part[g];
         const double beta = 0.5 * tau * tot;
-        double wr[8], wc[8];
+        double wr[RB], wc[RB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < RB; ++i) {
           const int r = ty + 16 * i, c = tx + 16 * i;
           wr[i] = r > k ? pr[i] - beta * vr[i] : 0.0;
           wc[i] = c > k ? ps[c] - beta * vc[i] : 0.0;
         }
         // A <- A - v w^T - w v^T (entries with an index <= k are unchanged)
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) A[i][q] -= vr[i] * wc[q] + wr[i] * vc[q];
+          for (int q = 0; q < RB; ++q) A[i][q] -= vr[i] * wc[q] + wr[i] * vc[q];
       }
       __syncthreads();   // xs, ps, part are reused by the next step
     }
     // the trailing 2 x 2 (or smaller) block
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < RB; ++q) {
         const int r = ty + 16 * i, c = tx + 16 * q;
         if (K >= 2 && r == K - 2 && c == K - 2) dg[K - 2] = A[i][q];
         if (K >= 2 && r == K - 1 && c == K - 2) eo[K - 2] = A[i][q];
@@ -373,20 +380,20 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
   // ---- 3. Q = H_0 H_1 ... H_{K-3} Z with Z in registers: thread (cg, rl) =
   // (tid / 16, tid % 16) holds Z[rl + 16i][cg + 16q]; a DPP row is one column strip
   const int rl = tid & 15, cg = tid >> 4;
-  double Z[8][8];
+  double Z[RB][RB];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < RB; ++q) {
       const int r = rl + 16 * i, c = cg + 16 * q;
       Z[i][q] = (r < K && c < K) ? L[r * ld + c] : 0.0;
     }
   if (K >= 3) {
-    double vn[8];
+    double vn[RB];
     double taun = 0.0;
     auto load_v = [&](int k) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < RB; ++i) {
         const int r = rl + 16 * i;
         vn[i] = (r > k && r < K) ? gld(&Vs[k * K + r - k - 1]) : 0.0;
       }
@@ -394,20 +401,20 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
     };
     load_v(K - 3);
     for (int k = K - 3; k >= 0; --k) {
-      double v[8];
+      double v[RB];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = vn[i];
+      for (int i = 0; i < RB; ++i) v[i] = vn[i];
       const double tau = taun;
       if (k > 0) load_v(k - 1);   // next reflector, in flight during this one
       if (tau != 0.0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < RB; ++q) {
           double s = 0.0;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) s = fma(v[i], Z[i][q], s);
+          for (int i = 0; i < RB; ++i) s = fma(v[i], Z[i][q], s);
           const double y = tau * row16_sum(s);
 #pragma unroll
-          for (int i = 0; i < 8; ++i) Z[i][q] = fma(-v[i], y, Z[i][q]);
+          for (int i = 0; i < RB; ++i) Z[i][q] = fma(-v[i], y, Z[i][q]);
         }
       }
     }
@@ -428,9 +435,9 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
   if (tid == 0) atomicMax(&st->pad, min(sh_iters / K, 255));
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < RB; ++q) {
       const int r = rl + 16 * i, c = cg + 16 * q;
       if (r < K && c < K) gst(&a.Q[r * K + rankpos[c]], Z[i][q]);
     }
@@ -438,9 +445,12 @@ __global__ __launch_bounds__(NT) void eig_kernel(const SmallArgs* __restrict__ a
 
 }  // namespace
 
-hipError_t launch_eig(const SmallArgs* args, int n, double*, hipStream_t s, GlobalState* st) {
+hipError_t launch_eig(const SmallArgs* args, int n, int max_k, hipStream_t s, GlobalState* st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(eig_kernel, dim3(n), dim3(NT), 0, s, args, st);
+  if (max_k <= 64)
+    hipLaunchKernelGGL(eig_kernel<64>, dim3(n), dim3(NT), 0, s, args, st);
+  else
+    hipLaunchKernelGGL(eig_kernel<128>, dim3(n), dim3(NT), 0, s, args, st);
   return hipGetLastError();
 }
 

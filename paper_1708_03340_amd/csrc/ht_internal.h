@@ -164,7 +164,8 @@ hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s)
 hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);
 hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st);
-hipError_t launch_eig(const SmallArgs* args, int n, double* scratch, hipStream_t s, GlobalState* st);
+// max_k: the largest K among the args (picks the instantiation)
+hipError_t launch_eig(const SmallArgs* args, int n, int max_k, hipStream_t s, GlobalState* st);
 hipError_t launch_rank_select(const SmallArgs* args, const StateRec* r, int n, hipStream_t s);
 hipError_t launch_proj_prep(const SmallArgs* args, int n, const GlobalState* st, hipStream_t s);
 hipError_t launch_root_norm(const StateRec* r, int n, hipStream_t s);

@@ -14,7 +14,8 @@ constexpr int NT = DNT;
 
 
 // ------------------------------------------------------------------ ranks
-// One workgroup per tensor: its nodes are args[a0 .. a0 + na).
+// One workgroup per tensor: its nodes are args[a0 .. a0 + na) (all nodes of
+// the tensor, or a group of them).
 __global__ void rank_kernel(const SmallArgs* __restrict__ all_args, const StateRec* __restrict__ recs) {
   __shared__ double red[NT / 64];
   __shared__ int idx_t1, idx_t2;
@@ -32,19 +33,24 @@ __global__ void rank_kernel(const SmallArgs* __restrict__ all_args, const StateR
     if (args[i].node == t2) idx_t2 = i;
   }
   __syncthreads();
+  // a group of nodes without the sons of the root (decomposed later) uses
+  // the norm and threshold the group with them stored
+  const bool has_root_sons = idx_t1 >= 0;
   double part = 0.0;
-  if (idx_t1 >= 0)
+  if (has_root_sons)
     for (int i = tid; i < args[idx_t1].K; i += NT) part += args[idx_t1].lam[i];
   const double n2 = wg_sum(part, red);
   double thr;
-  if (R.rel) {
+  if (!has_root_sons) {
+    thr = st->thr;
+  } else if (R.rel) {
     thr = eps * eps * n2 / (double)(2 * d - 3);
   } else {
     const long long g = st->e_D + st->log2_scale;
     const double en = ldexp(eps, (int)(-g));
     thr = en * en / (double)(2 * d - 3);
   }
-  if (tid == 0) { st->norm2_units = n2; st->thr = thr; }
+  if (tid == 0 && has_root_sons) { st->norm2_units = n2; st->thr = thr; }
   for (int i = tid; i < n; i += NT) {
     const SmallArgs& a = args[i];
     int r;
