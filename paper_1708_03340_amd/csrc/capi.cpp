@@ -148,6 +148,30 @@ GemmDesc blank_desc() {
   return d;
 }
 
+// Per-descriptor eligibility for the streamed kernel (small operand in LDS,
+// the other streamed): -1 none, 0 with S = A, 1 with S = B^T.
+int sb_want(const GemmDesc& d) {
+  int kt = 0;
+  if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
+  else kt = d.K;
+  if (d.kr || d.KB != 1 || kt < 1 || kt > 128) return -1;
+  const long long nbt = d.nbatch;
+  if (d.M <= 128 && d.sBn == 1 && d.N * nbt >= 256) return 0;   // S = A, T = B
+  if (d.N <= 128 && d.sAm == 1 && d.M * nbt >= 256) return 1;   // S = B^T, T = A^T
+  return -1;
+}
+
+// Shapes the split-K kernel takes (result at most 128 x 128, above 64 x 64).
+bool rk_shape(const GemmDesc& d) {
+  return !(d.kr || d.nseg > 0 || d.nbatch != 1 || d.M > 128 || d.N > 128 || d.M <= 64 || d.N <= 64 || d.K < 1 ||
+           !(d.sAk == 1 || d.sAm == 1) || !(d.sBk == 1 || d.sBn == 1));
+}
+
+// B is A^T of the same matrix (a Gram matrix).
+bool rk_gram(const GemmDesc& d) {
+  return d.A == d.B && d.M == d.N && d.sAm == d.sBn && d.sAk == d.sBk && d.sAkb == d.sBkb;
+}
+
 // Adds one GEMM launch over `descs` (all sharing types, math, mode, layouts).
 // The launch of a GEMM over `descs` (all sharing types, math, mode and
 // layouts): kernel choice, tiling and split; the descriptors are not stored.
@@ -177,15 +201,12 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
     long long items = 0;
     bool k64 = true;
     for (const auto& d : descs) {
+      if (!ok) break;
       int kt = 0;
       if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
       else kt = d.K;
       if (kt % 64) k64 = false;
-      if (d.kr || d.KB != 1 || kt < 1 || kt > 128) { ok = false; break; }
-      const long long nbt = d.nbatch;
-      const bool c0 = d.M <= 128 && d.sBn == 1 && d.N * nbt >= 256;   // S = A, T = B
-      const bool c1 = d.N <= 128 && d.sAm == 1 && d.M * nbt >= 256;   // S = B^T, T = A^T
-      const int want = c0 ? 0 : (c1 ? 1 : -1);
+      const int want = sb_want(d);
       if (want < 0 || (swap >= 0 && want != swap)) { ok = false; break; }
       swap = want;
       const int ns = swap ? d.M : d.N;
@@ -209,9 +230,8 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
     bool ok = true, sym = tA == tB;
     long long chunks = 0;
     for (const auto& d : descs) {
-      if (d.kr || d.nseg > 0 || d.nbatch != 1 || d.M > 128 || d.N > 128 || d.M <= 64 || d.N <= 64 || d.K < 1 ||
-          !(d.sAk == 1 || d.sAm == 1) || !(d.sBk == 1 || d.sBn == 1)) { ok = false; break; }
-      if (!(d.A == d.B && d.M == d.N && d.sAm == d.sBn && d.sAk == d.sBk && d.sAkb == d.sBkb)) sym = false;
+      if (!rk_shape(d)) { ok = false; break; }
+      if (!rk_gram(d)) sym = false;
       chunks = std::max<long long>(chunks, (long long)((d.K + 15) / 16) * d.KB);
     }
     if (ok && (sym || sym_out)) {
@@ -368,20 +388,29 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
     return gemm_op(v, q.tA, q.tB, q.tC, q.math, q.mode, q.a_kcontig, q.b_kcontig, proto.acc64_req,
                    proto.tblocks, proto.sym_out);
   };
+  // the kernel gemm_op would pick for the descriptor alone
   std::vector<std::vector<GemmDesc>> cls(5);
   for (const auto& d : descs) {
-    const Op one = decide({d});
-    const int c = one.g.sb ? (one.g.sb_swap ? 1 : 0) : (one.g.rk ? 1 + one.g.rk_sym : 4);
+    int c = 4;
+    if (q.math == MATH_F64 && q.mode == GEMM_STORE) {
+      const int w = sb_want(d);
+      if (w >= 0) c = w;
+    } else if (q.math == MATH_F64 && q.mode == GEMM_ATOMIC && rk_shape(d) && d.M == d.N) {
+      const bool gram = q.tA == q.tB && rk_gram(d);
+      if (gram || proto.sym_out) c = gram ? 2 : 3;
+    }
     cls[c].push_back(d);
   }
   constexpr long long kGridMax = 65535;
-  for (const auto& v : cls) {
+  for (int ci = 0; ci < 5; ++ci) {
+    const auto& v = cls[ci];
+    const bool tiled = ci == 4;   // only the tiled kernels put the batch on a grid axis
     size_t i = 0;
     while (i < v.size()) {
       std::vector<GemmDesc> chunk;
       long long mb = 1;
       while (i < v.size()) {
-        const long long nb = std::max<long long>(mb, v[i].nbatch);
+        const long long nb = tiled ? std::max<long long>(mb, v[i].nbatch) : 1;
         if (!chunk.empty() && (long long)(chunk.size() + 1) * nb > kGridMax) break;
         mb = nb;
         chunk.push_back(v[i++]);
@@ -404,45 +433,44 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
 // correctness needs (the problems share no written memory).
 ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
   const int n = (int)plans.size();
-  std::vector<std::vector<std::string>> key(n);
-  std::vector<std::map<std::string, int>> pos(n);
+  // steps as integer ids: (kind, label, occurrence of the pair in the plan)
+  std::map<std::string, int> ids;
+  std::vector<std::vector<int>> key(n);
   for (int p = 0; p < n; ++p) {
     std::map<std::string, int> occ;
-    for (size_t i = 0; i < plans[p].ops.size(); ++i) {
-      const Op& op = plans[p].ops[i];
+    for (const Op& op : plans[p].ops) {
       const std::string base = std::to_string(op.kind) + "|" + (op.label ? op.label : "");
       const std::string k = base + "|" + std::to_string(occ[base]++);
-      key[p].push_back(k);
-      pos[p][k] = (int)i;
+      auto it = ids.emplace(k, (int)ids.size()).first;
+      key[p].push_back(it->second);
     }
   }
-  std::vector<int> head(n, 0);
+  // a step may be taken when every plan that still holds it holds it at its
+  // head: left[k] (plans not yet past k) equals at_head[k]
+  const int nk = (int)ids.size();
+  std::vector<int> left(nk, 0), at_head(nk, 0), head(n, 0);
+  for (int p = 0; p < n; ++p)
+    for (int k : key[p]) ++left[k];
   auto done = [&](int p) { return head[p] >= (int)key[p].size(); };
+  for (int p = 0; p < n; ++p)
+    if (!done(p)) ++at_head[key[p][0]];
   while (true) {
     int first = -1;
     for (int p = 0; p < n && first < 0; ++p)
       if (!done(p)) first = p;
     if (first < 0) break;
-    std::string chosen;
-    std::set<std::string> tried;
-    for (int p = first; p < n && chosen.empty(); ++p) {
-      if (done(p)) continue;
-      const std::string& k = key[p][head[p]];
-      if (!tried.insert(k).second) continue;
-      bool ok = true;
-      for (int q = 0; q < n && ok; ++q) {
-        if (done(q)) continue;
-        auto it = pos[q].find(k);
-        if (it != pos[q].end() && it->second != head[q]) ok = false;
-      }
-      if (ok) chosen = k;
-    }
-    if (chosen.empty()) chosen = key[first][head[first]];
+    int chosen = -1;
+    for (int p = first; p < n && chosen < 0; ++p)
+      if (!done(p) && left[key[p][head[p]]] == at_head[key[p][head[p]]]) chosen = key[p][head[p]];
+    if (chosen < 0) chosen = key[first][head[first]];
     std::vector<std::pair<int, const Op*>> grp;
     for (int p = 0; p < n; ++p)
       if (!done(p) && key[p][head[p]] == chosen) {
         grp.push_back({p, &plans[p].ops[head[p]]});
+        --left[chosen];
+        --at_head[chosen];
         ++head[p];
+        if (!done(p)) ++at_head[key[p][head[p]]];
       }
     const Op& o0 = *grp[0].second;
     auto tab = [&](int p, size_t off) { return plans[p].table.data() + off; };
@@ -1381,10 +1409,11 @@ ht_status ht_tree(int32_t d, int32_t* parent, int32_t* son1, int32_t* son2, int3
 // ------------------------------------------------------------------ truncation
 // overlap: run the upper part of the tree on the library's second stream
 // (see below); off for the plans of a batch, which are merged instead.
+// used (optional): the workspace bytes the plan takes (as need reports).
 static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
                                 const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
                                 int64_t* out_scale, uint32_t* flags, double* out_sigma, void* ws,
-                                Plan& P, size_t* need, bool overlap = true) {
+                                Plan& P, size_t* need, bool overlap = true, size_t* used = nullptr) {
   (void)ctx;
   if (!opts) return fail(HT_EINVAL, "opts is NULL");
   if (opts->mode != HT_RANK_FIXED && opts->mode != HT_RANK_TOL) return fail(HT_EINVAL, "bad rank mode");
@@ -1606,6 +1635,7 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
   }
   (void)tsz;
   if (need) *need = align256(A.off) + 256;
+  if (used) *used = align256(A.off) + 256;
   return HT_OK;
 }
 
@@ -1657,38 +1687,39 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
 static ht_status build_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
                                         const double* coef, const ht_trunc_opts* opts, const ht_desc* out,
                                         int32_t* const* out_ranks, int64_t* out_scale, uint32_t* flags,
-                                        double* const* out_sigma, void* ws, Plan& M, size_t* need) {
+                                        double* const* out_sigma, void* ws, Plan& M, size_t* need,
+                                        size_t* used = nullptr) {
   if (count < 1) return fail(HT_EINVAL, "count must be >= 1");
   if (!X || !n_in || !opts) return fail(HT_EINVAL, "X, n_in or opts is NULL");
   if (!need && (!out || !out_scale)) return fail(HT_EINVAL, "out or out_log2_scale is NULL");
-  std::vector<Plan> plans(count);
-  size_t off = 0, total = 0;
+  std::vector<Plan> plans(need ? 0 : count);
+  size_t off = 0;
   int64_t first = 0;
   for (int c = 0; c < count; ++c) {
     if (n_in[c] < 1) return fail(HT_EINVAL, "n_in[" + std::to_string(c) + "] must be >= 1");
     const ht_desc* Xc = X + first;
     size_t nc = 0;
-    Plan dry;
-    ht_status st = build_truncate(ctx, Xc, nullptr, n_in[c], &opts[c], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                  nullptr, dry, &nc);
-    if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
-    nc = align256(nc);
+    ht_status st;
     if (need) {
-      total += nc;
+      Plan dry;
+      st = build_truncate(ctx, Xc, nullptr, n_in[c], &opts[c], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          dry, &nc);
     } else {
+      // the problem's part of the workspace starts where the previous one ends
       char* wc = reinterpret_cast<char*>(ws) + off;
       st = build_truncate(ctx, Xc, coef ? coef + first : nullptr, n_in[c], &opts[c], &out[c],
                           out_ranks ? out_ranks[c] : nullptr, out_scale + c, flags ? flags + c : nullptr,
-                          out_sigma ? out_sigma[c] : nullptr, wc, plans[c], nullptr, false);
-      if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
+                          out_sigma ? out_sigma[c] : nullptr, wc, plans[c], nullptr, false, &nc);
     }
-    off += nc;
+    if (st) return fail(st, "tensor " + std::to_string(c) + ": " + g_last_error);
+    off += align256(nc);
     first += n_in[c];
   }
   if (need) {
-    *need = total;
+    *need = off;
     return HT_OK;
   }
+  if (used) *used = off;
   return merge_plans(plans, M);
 }
 
@@ -1727,16 +1758,24 @@ ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, 
                               int32_t* const* out_ranks, int64_t* out_log2_scale, uint32_t* flags,
                               double* const* out_sigma, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  if (count < 1 || !X || !n_in) return fail(HT_EINVAL, "count, X or n_in");
+  int64_t tot = 0;
+  for (int c = 0; c < count; ++c) tot += std::max(0, n_in[c]);
+  for (int64_t i = 0; i < tot; ++i) {
+    ht_status s = check_desc(&X[i], "X[i]");
+    if (s) return s;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(HT_EWORKSPACE, "workspace must be 256-byte aligned");
+  // the plans are built once, each problem taking the next part of the
+  // workspace; nothing is launched unless the whole of it fits
+  Plan M;
   size_t need = 0;
-  ht_status st = ht_truncate_batched_workspace(ctx, count, X, n_in, opts, &need);
+  ht_status st = build_truncate_batched(ctx, count, X, n_in, coef, opts, out, out_ranks, out_log2_scale, flags,
+                                        out_sigma, ws, M, nullptr, &need);
   if (st) return st;
-  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+  if (ws_bytes < need)
     return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
   HT_HIP(hipSetDevice(ctx->device));
-  Plan M;
-  st = build_truncate_batched(ctx, count, X, n_in, coef, opts, out, out_ranks, out_log2_scale, flags, out_sigma,
-                              ws, M, nullptr);
-  if (st) return st;
   return run_plan(ctx, M, reinterpret_cast<hipStream_t>(stream));
 }
 
