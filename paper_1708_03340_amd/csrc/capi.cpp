@@ -523,10 +523,10 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           op.bytes_alg += b.bytes_alg;
         }
         if (o0.kind == OP_EIG) {
-          // the eigensolver by order: nodes up to 64 run two to a CU
-          std::vector<SmallArgs> lo, hi;
-          for (const auto& x : sa) (x.K <= 64 ? lo : hi).push_back(x);
-          for (const auto* part : {&lo, &hi}) {
+          // the eigensolver by order: nodes up to 96 run two to a CU
+          std::vector<SmallArgs> lo, mid, hi;
+          for (const auto& x : sa) (x.K <= 64 ? lo : (x.K <= 96 ? mid : hi)).push_back(x);
+          for (const auto* part : {&lo, &mid, &hi}) {
             if (part->empty()) continue;
             Op e = op;
             e.toff = put(M, *part);
@@ -797,7 +797,7 @@ std::string kernel_name(const Op& op) {
              (op.g.math == MATH_F32 && op.g.acc64 ? "true" : "false") + ">";
     case OP_CHOL1: case OP_CHOL2: return "chol_kernel";
     case OP_FINISHR: return "finish_r_kernel";
-    case OP_EIG: return op.i0 <= 64 ? "eig_kernel<64>" : "eig_kernel<128>";
+    case OP_EIG: return op.i0 <= 64 ? "eig_kernel<64>" : (op.i0 <= 96 ? "eig_kernel<96>" : "eig_kernel<128>");
     case OP_RANK: return "rank_kernel";
     case OP_PROJPREP: return "proj_prep_kernel";
     case OP_SIGMA: return "sigma_kernel";

@@ -27,8 +27,6 @@ namespace {
 
 constexpr int NT = DNT;
 
-__shared__ double g_trash[NT];   // sink for the stores of out-of-range lanes
-
 // 1 / sqrt(x), x > 0 normal: hardware estimate (relative error ~5e-8) and one
 // third-order step, y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
 __device__ __forceinline__ double rsqrt3(double x) {
@@ -46,18 +44,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 enum : int { SWEEP_NONE = 0, SWEEP_ROT = 1, SWEEP_DONE = 2 };
 
-// KT: the largest order the instantiation takes (64 or 128).  At KT = 64 the
-// LDS of a node is a quarter of that at 128 and two nodes share a CU (the
-// registers of the rotation blocks keep it from four).
+// KT: the largest order the instantiation takes (64, 96 or 128).  Up to 96 a
+// node's LDS is at most 80 KB and two nodes share a CU (the registers of the
+// rotation blocks keep it from more).
 template <int KT>
-__global__ __launch_bounds__(NT, KT == 64 ? 2 : 1) void eig_kernel(const SmallArgs* __restrict__ args,
+__global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallArgs* __restrict__ args,
                                                                    GlobalState* st) {
   constexpr int RB = KT / 16;                    // row (column) blocks of 16
-  __shared__ double L[KT * (KT + 1)];            // Z during the QL phase
+  __shared__ double L[KT * (KT + 1)];            // Z during the QL phase (column K: store sink)
   __shared__ double dg[KT], eo[KT];
-  __shared__ double rcs[2][KT], rss[2][KT];      // rotations of two sweeps
+  // the vectors of the tridiagonalisation and, later, the rotations of two
+  // QL sweeps share one buffer
+  __shared__ double vbuf[4 * KT];
+  double* const xs = vbuf;
+  double* const ps = vbuf + KT;
+  double (*const rcs)[KT] = reinterpret_cast<double (*)[KT]>(vbuf);
+  double (*const rss)[KT] = reinterpret_cast<double (*)[KT]>(vbuf + 2 * KT);
   __shared__ int sw_state[2], sw_m[2], sw_lo[2];
-  __shared__ double xs[KT], ps[KT];
   __shared__ double part[16];
   __shared__ int rankpos[KT];
   __shared__ int sh_iters;
@@ -97,8 +100,9 @@ __global__ __launch_bounds__(NT, KT == 64 ? 2 : 1) void eig_kernel(const SmallAr
       __syncthreads();
       // every wave forms ||x||^2 itself (the same sum in the same order)
       const double x0 = xs[k + 1];
-      const double nrm2 = KT > 64 ? wave_sum(xs[lane] * xs[lane] + xs[lane + 64] * xs[lane + 64])
-                                  : wave_sum(xs[lane] * xs[lane]);
+      double hi = 0.0;   // entries 64 .. KT-1 (lanes past KT-64 add zero)
+      if (KT > 64) hi = xs[min(lane + 64, KT - 1)] * (lane + 64 < KT ? 1.0 : 0.0);
+      const double nrm2 = wave_sum(xs[lane] * xs[lane] + hi * hi);
       double tau = 0.0, alpha = x0;
       if (nrm2 > 0.0) {
         alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(NT, KT == 64 ? 2 : 1) void eig_kernel(const SmallAr
             carry = i - u >= lo ? nc : carry;
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) *(i - u >= lo ? &row[i - u + 1] : &g_trash[tid]) = o[u];
+          for (int u = 0; u < 8; ++u) *(i - u >= lo ? &row[i - u + 1] : &row[K]) = o[u];
         }
         row[lo] = carry;
       }
@@ -449,6 +453,8 @@ hipError_t launch_eig(const SmallArgs* args, int n, int max_k, hipStream_t s, Gl
   if (n <= 0) return hipSuccess;
   if (max_k <= 64)
     hipLaunchKernelGGL(eig_kernel<64>, dim3(n), dim3(NT), 0, s, args, st);
+  else if (max_k <= 96)
+    hipLaunchKernelGGL(eig_kernel<96>, dim3(n), dim3(NT), 0, s, args, st);
   else
     hipLaunchKernelGGL(eig_kernel<128>, dim3(n), dim3(NT), 0, s, args, st);
   return hipGetLastError();
