@@ -1191,7 +1191,12 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       dg.push_back(g);
     }
     g_label = "inner_gram_sweep1";
-    add_gemm(P, dg, T, T, F64, smath, GEMM_ATOMIC, true, true);
+    // the operands are float64 here; where the split-K Gram kernel takes the
+    // shape, its FP64 matrix cores are faster than the FP32 kernels on these
+    // shapes, so the mixed path uses them too
+    bool rk_all = !dg.empty();
+    for (const auto& g : dg) rk_all = rk_all && rk_shape(g) && rk_gram(g);
+    add_gemm(P, dg, T, T, F64, rk_all ? MATH_F64 : smath, GEMM_ATOMIC, true, true);
     {
       g_label = "inner_chol1";
       auto a = small_args(nodes, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
