@@ -119,17 +119,17 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
           dropped[g] = drop ? 1 : 0;
           if (drop) any = 1;
         }
-        if (drop) {
-          blockdrop = true;
-          mydrop = mydrop || r == j;
-          continue;
-        }
-        const double ip = rcp_nr(pj);
+        // branch-free: a dropped pivot eliminates nothing (multiplier 0), so
+        // the updates stay in place whatever the pivot
+        blockdrop = blockdrop || drop;
+        mydrop = mydrop || (drop && r == j);
+        const double pv = drop ? 1.0 : pj;
+        const double ip = rcp_nr(pv);
         if (r == j) {
-          rs = rsqrt_nr(pj);
-          ar[j] = pj;   // U_jj is the (possibly clamped) pivot
+          rs = rsqrt_nr(pv);
+          ar[j] = pv;   // U_jj is the (possibly clamped) pivot
         }
-        const double m = r > j ? ar[j] * ip : 0.0;
+        const double m = (r > j && !drop) ? ar[j] * ip : 0.0;
 #pragma unroll
         for (int c = j + 1; c < 16; ++c) ar[c] = fma(-m, lane_val(ar[c], j), ar[c]);
 #pragma unroll
