@@ -199,13 +199,14 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
     bool ok = math == MATH_F64 && mode == GEMM_STORE;
     int swap = -1;
     long long items = 0;
-    bool k64 = true;
+    bool k64 = true, four = true;
     for (const auto& d : descs) {
       if (!ok) break;
       int kt = 0;
       if (d.nseg > 0) for (int s = 0; s < d.nseg; ++s) kt += d.segK[s];
       else kt = d.K;
       if (kt % 64) k64 = false;
+      if (kt <= 96) four = false;   // four 32-deep chunks: the ring kernel
       const int want = sb_want(d);
       if (want < 0 || (swap >= 0 && want != swap)) { ok = false; break; }
       swap = want;
@@ -218,6 +219,7 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
       op.g.sb_swap = swap == 1;
       op.g.sb_wn = 1;
       op.g.sb_cd = k64 ? 64 : 32;
+      op.g.sb_ring = four;
       const long long per = (512 + (long long)descs.size() - 1) / (long long)descs.size();
       op.g.sb_grid = (int)std::max<long long>(1, std::min(per, items));
     }
@@ -780,6 +782,10 @@ std::string kernel_name(const Op& op) {
   auto tn = [](int t) { return t == F32 ? "float" : "double"; };
   switch (op.kind) {
     case OP_GEMM:   // the template arguments of the kernel that launch_gemm picks
+      if (op.g.sb && op.g.sb_ring) {
+        const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
+        return std::string("gemm_sb_ring_kernel<") + tn(ts) + "," + tn(tt) + "," + tn(op.g.tC) + ">";
+      }
       if (op.g.sb) {
         const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
         return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + ",1," + std::to_string(op.g.sb_cd == 64 ? 64 : 32) +

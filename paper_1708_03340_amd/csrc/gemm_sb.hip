@@ -14,6 +14,9 @@
 // products of the previous chunk.  S is reloaded only when the batch changes
 // and S has a batch stride.
 //
+// Reductions of 97 .. 128 use gemm_sb_ring_kernel below (four operand
+// buffers, loads two chunks ahead).
+//
 // GemmDesc mapping (swap = 0): S = A (M x K), T = B (K x N), C as given.
 // swap = 1: S = B^T (N x K), T = A^T (K x M), out[m][n] = C[n][m]: the small
 // operand is B and A is streamed along M.  Segments (GemmDesc::nseg) split
@@ -28,6 +31,10 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int SB_K = 128;          // largest reduction length
 constexpr int SB_MP = 128 + 4;     // LDS row length of S (padded)
 constexpr int SB_TN = 128;         // streamed columns per tile
+
+// Sink for the stores of lanes outside the result (never read): with it every
+// lane stores, and no store sits behind a branch.
+__device__ double g_sb_sink[512];
 
 template <typename T>
 __device__ __forceinline__ double ld_as_double(const char* p) {
@@ -177,10 +184,151 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
   }
 }
 
+// The same product for reductions of 97 .. 128 (four 32-deep chunks per
+// item), with a ring of four operand buffers: the loads of a chunk are issued
+// two chunks before it is needed, and those of the next item's first three
+// chunks before the item's results are stored.  The vector-memory counter
+// counts loads and stores in issue order; here the first wait with a store
+// ahead of it comes two chunks after the stores, which have drained by then.
+// Every item runs the same straight-line sequence (past the last item the
+// loads repeat its last chunk), so every wait count is fixed.
+template <typename TS, typename TT, typename TC>
+__global__ __launch_bounds__(512, 1) void gemm_sb_ring_kernel(const GemmDesc* __restrict__ descs, int swap) {
+  constexpr int NT = 512;
+  __shared__ double Ss[SB_K][SB_MP];
+  __shared__ const char* trow[SB_K];
+  __shared__ const char* srow[SB_K];
+
+  const GemmDesc& D = descs[blockIdx.y];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Ms = swap ? D.N : D.M;
+  const int Ns = swap ? D.M : D.N;
+  const int nseg = D.nseg > 0 ? D.nseg : 1;
+  const int esS = sizeof(TS), esT = sizeof(TT);
+  const int64_t s_m = (swap ? D.sBn : D.sAm) * esS;
+  const int64_t t_n = (swap ? D.sAm : D.sBn) * esT;
+  const int64_t s_b = (swap ? D.sBb : D.sAb) * esS;
+  const int64_t t_b = (swap ? D.sAb : D.sBb) * esT;
+  const int64_t c_m = swap ? D.sCn : D.sCm, c_n = swap ? D.sCm : D.sCn;
+  int Kt = 0;
+  for (int s = 0; s < nseg; ++s) Kt += D.nseg > 0 ? D.segK[s] : D.K;
+  if (tid < SB_K) {
+    const int k = min(tid, Kt - 1);
+    int s = 0, kofs = 0;
+    while (s + 1 < nseg && k >= kofs + (D.nseg > 0 ? D.segK[s] : D.K)) {
+      kofs += D.nseg > 0 ? D.segK[s] : D.K;
+      ++s;
+    }
+    const int kl = k - kofs;
+    const char* Aseg = reinterpret_cast<const char*>(D.nseg > 0 ? D.segA[s] : D.A);
+    const int64_t sAk = D.nseg > 0 ? D.segAk[s] : D.sAk;
+    const int64_t boff = D.nseg > 0 ? D.segBoff[s] : 0;
+    const char* Bb = reinterpret_cast<const char*>(D.B);
+    if (!swap) {
+      srow[tid] = Aseg + kl * sAk * esS;
+      trow[tid] = Bb + (boff + kl * D.sBk) * esT;
+    } else {
+      srow[tid] = Bb + (boff + kl * D.sBk) * esS;
+      trow[tid] = Aseg + kl * sAk * esT;
+    }
+  }
+  const int tilesN = (Ns + SB_TN - 1) / SB_TN;
+  const int nitems = tilesN * D.nbatch;
+  const int it0 = blockIdx.x;
+  if (it0 >= nitems) return;
+  const int nq = (nitems - it0 + (int)gridDim.x - 1) / (int)gridDim.x;   // items of this workgroup
+
+  auto load_S = [&](int b) {
+    __syncthreads();
+    for (int idx = tid; idx < SB_K * 128; idx += NT) {
+      const int k = idx >> 7, m = idx & 127;
+      double v = 0.0;
+      if (k < Kt && m < Ms) v = ld_as_double<TS>(srow[k] + b * s_b + m * s_m);
+      Ss[k][m] = v;
+    }
+    __syncthreads();
+  };
+  // chunk c (32 deep) of the q-th item of this workgroup, q clamped to the last
+  auto load_T = [&](int q, int c, double (&bf)[8]) {
+    const int it = it0 + min(q, nq - 1) * (int)gridDim.x;
+    const int b = it / tilesN, tn = it % tilesN;
+    const int n = min(tn * SB_TN + wave * 16 + (lane & 15), Ns - 1);
+    const int64_t noff = (int64_t)b * t_b + n * t_n;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) bf[kk] = ld_as_double<TT>(trow[32 * c + 4 * kk + (lane >> 4)] + noff);
+  };
+  // the scale is always loaded (from the descriptor itself without a device
+  // factor) so that no load sits behind a branch
+  const double av = gld(D.alpha_dev ? D.alpha_dev : &D.alpha);
+  const double alpha = D.alpha_dev ? D.alpha * av : av;
+
+  int cur_b = it0 / tilesN;
+  __syncthreads();   // row tables visible
+  load_S(cur_b);
+  double B0[8], B1[8], B2[8], B3[8];
+  load_T(0, 0, B0);
+  load_T(0, 1, B1);
+  load_T(0, 2, B2);
+  doublex4 acc[8];
+  auto chunk = [&](int c, const double (&bf)[8]) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 32 * c + 4 * kk + (lane >> 4);
+      double a[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = Ss[k][16 * i + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bf[kk], acc[i], 0, 0, 0);
+    }
+  };
+  for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = doublex4{0, 0, 0, 0};
+    // each prefetch is issued after the chunk it follows: with three
+    // buffers of eight loads and the 32 stores of an item at most 56 memory
+    // operations are outstanding at any wait (the counter holds 63)
+    chunk(0, B0);
+    load_T(q, 3, B3);
+    chunk(1, B1);
+    load_T(q + 1, 0, B0);
+    chunk(2, B2);
+    load_T(q + 1, 1, B1);
+    chunk(3, B3);
+    load_T(q + 1, 2, B2);
+    // epilogue: lane holds rows 16i + 4v + lane/16, column lane%16 of the wave's strip
+    {
+      const int it = it0 + q * (int)gridDim.x;
+      const int b = it / tilesN, tn = it % tilesN;
+      TC* Cb = reinterpret_cast<TC*>(D.C) + (int64_t)b * D.sCb;
+      const int n = tn * SB_TN + wave * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * i + 4 * v + (lane >> 4);
+          const bool in = m < Ms && n < Ns;
+          TC* p = in ? Cb + (m * c_m + n * c_n) : reinterpret_cast<TC*>(&g_sb_sink[tid]);
+          gst(p, (TC)(alpha * acc[i][v]));
+        }
+    }
+    if (q + 1 < nq && s_b != 0) {
+      const int nb = (it0 + (q + 1) * (int)gridDim.x) / tilesN;
+      if (nb != cur_b) {
+        cur_b = nb;
+        load_S(cur_b);
+      }
+    }
+  }
+}
+
 template <typename TS, typename TT>
 hipError_t go_sb(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.sb_grid, g.ndesc, 1);
-  if (g.sb_cd == 64)
+  if (g.sb_ring && g.tC == F64)
+    hipLaunchKernelGGL((gemm_sb_ring_kernel<TS, TT, double>), grid, dim3(512), 0, s, g.descs, g.sb_swap);
+  else if (g.sb_ring)
+    hipLaunchKernelGGL((gemm_sb_ring_kernel<TS, TT, float>), grid, dim3(512), 0, s, g.descs, g.sb_swap);
+  else if (g.sb_cd == 64)
     hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 64>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
   else
     hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 32>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
