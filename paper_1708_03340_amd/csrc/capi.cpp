@@ -156,8 +156,13 @@ int sb_want(const GemmDesc& d) {
   else kt = d.K;
   if (d.kr || d.KB != 1 || kt < 1 || kt > 128) return -1;
   const long long nbt = d.nbatch;
+  // the streamed operand contiguous along its free index first; one
+  // contiguous along the reduction also streams faster than the tiled kernels
+  // take it (each lane's eight loads of a chunk cover 32 consecutive k)
   if (d.M <= 128 && d.sBn == 1 && d.N * nbt >= 256) return 0;   // S = A, T = B
   if (d.N <= 128 && d.sAm == 1 && d.M * nbt >= 256) return 1;   // S = B^T, T = A^T
+  if (d.M <= 128 && d.N * nbt >= 256) return 0;
+  if (d.N <= 128 && d.M * nbt >= 256) return 1;
   return -1;
 }
 
@@ -628,6 +633,10 @@ struct ht_context {
   std::mutex run_mu;                     // one plan at a time uses the second stream
   hipStream_t side = nullptr;            // second stream (default priority), created on first use
   std::vector<hipEvent_t> sync_events;   // fork / join events
+  // the last batched call: its argument signature, merged plan and table
+  std::vector<unsigned char> bsig;
+  Plan bplan;
+  void* btable = nullptr;
   std::list<Plan> cache;   // most recent first
   bool prof = false;
   std::vector<hipEvent_t> free_events;
@@ -649,6 +658,8 @@ static hipEvent_t take_event(ht_context* c) {
 namespace {
 
 const size_t kCacheMax = 24;
+
+ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream);
 
 ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
   build_key(P);
@@ -677,6 +688,11 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
       ctx->cache.push_front(std::move(c));
     }
   }
+  return launch_plan(ctx, P, dtable, stream);
+}
+
+// Enqueues the launches of a plan whose argument table is at dtable.
+ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream) {
   char* tb = reinterpret_cast<char*>(dtable);
   bool forks = false;
   for (const auto& op : P.ops) forks = forks || op.kind == OP_FORK;
@@ -686,7 +702,7 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
     if (!ctx->side) HT_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
   }
   size_t nsync = 0;
-  for (auto& op : P.ops) {
+  for (const auto& op : P.ops) {
     if (op.kind == OP_FORK || op.kind == OP_JOIN) {
       if (nsync == ctx->sync_events.size()) {
         hipEvent_t ev = nullptr;
@@ -1398,6 +1414,7 @@ void ht_destroy_context(ht_context* ctx) {
   for (auto& e : ctx->free_events) (void)hipEventDestroy(e);
   for (auto& e : ctx->sync_events) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->btable) (void)hipFree(ctx->btable);
   delete ctx;
 }
 
@@ -1764,19 +1781,75 @@ ht_status ht_truncate_batched_workspace(ht_context* ctx, int32_t count, const ht
                                 nullptr, nullptr, M, bytes);
 }
 
+// Everything a batched plan depends on, as bytes: the contents of the
+// descriptors (shapes, dtypes, data pointers, scales), coefficients, options,
+// output pointers and the workspace.
+extern "C++" {
+static void sig_put(std::vector<unsigned char>& v, const void* p, size_t n) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  v.insert(v.end(), b, b + n);
+}
+template <typename T> static void sig_val(std::vector<unsigned char>& v, const T& x) { sig_put(v, &x, sizeof(T)); }
+static void sig_desc(std::vector<unsigned char>& v, const ht_desc& x) {
+  sig_val(v, x.d);
+  sig_val(v, x.frame_dtype);
+  sig_val(v, x.transfer_dtype);
+  sig_val(v, x.log2_scale);
+  const int nn = 2 * x.d - 1;
+  sig_put(v, x.n, sizeof(int64_t) * x.d);
+  sig_put(v, x.rank, sizeof(int32_t) * nn);
+  sig_put(v, x.leaf, sizeof(void*) * x.d);
+  sig_put(v, x.leaf_ld, sizeof(int64_t) * x.d);
+  sig_put(v, x.transfer, sizeof(void*) * nn);
+}
+}  // extern "C++"
+
 ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, const int32_t* n_in,
                               const double* coef, const ht_trunc_opts* opts, const ht_desc* out,
                               int32_t* const* out_ranks, int64_t* out_log2_scale, uint32_t* flags,
                               double* const* out_sigma, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
-  if (count < 1 || !X || !n_in) return fail(HT_EINVAL, "count, X or n_in");
+  if (count < 1 || !X || !n_in || !opts || !out) return fail(HT_EINVAL, "count, X, n_in, opts or out");
   int64_t tot = 0;
   for (int c = 0; c < count; ++c) tot += std::max(0, n_in[c]);
   for (int64_t i = 0; i < tot; ++i) {
     ht_status s = check_desc(&X[i], "X[i]");
     if (s) return s;
   }
+  for (int c = 0; c < count; ++c) {
+    ht_status s = check_desc(&out[c], "out[c]");
+    if (s) return s;
+  }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(HT_EWORKSPACE, "workspace must be 256-byte aligned");
+  // a call with the same arguments as the previous one reuses its plan
+  std::vector<unsigned char> sig;
+  sig_val(sig, count);
+  sig_put(sig, n_in, sizeof(int32_t) * count);
+  for (int64_t i = 0; i < tot; ++i) {
+    sig_desc(sig, X[i]);
+    sig_val(sig, coef ? coef[i] : 1.0);
+  }
+  for (int c = 0; c < count; ++c) {
+    const ht_trunc_opts& o = opts[c];
+    sig_val(sig, o.mode); sig_val(sig, o.eps); sig_val(sig, o.eps_relative); sig_val(sig, o.max_rank);
+    sig_val(sig, o.precision);
+    if (o.mode == HT_RANK_FIXED && o.ranks) sig_put(sig, o.ranks, sizeof(int32_t) * (2 * out[c].d - 1));
+    sig_desc(sig, out[c]);
+    sig_val(sig, out_ranks ? out_ranks[c] : nullptr);
+    sig_val(sig, out_sigma ? out_sigma[c] : nullptr);
+  }
+  sig_val(sig, out_log2_scale); sig_val(sig, flags); sig_val(sig, ws); sig_val(sig, ws_bytes);
+  HT_HIP(hipSetDevice(ctx->device));
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->btable && ctx->bsig == sig) {
+      Plan& B = ctx->bplan;
+      void* t = ctx->btable;
+      // launched outside the lock below would race a concurrent replacement;
+      // the launches only enqueue, so holding the lock is cheap
+      return launch_plan(ctx, B, t, reinterpret_cast<hipStream_t>(stream));
+    }
+  }
   // the plans are built once, each problem taking the next part of the
   // workspace; nothing is launched unless the whole of it fits
   Plan M;
@@ -1786,8 +1859,22 @@ ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, 
   if (st) return st;
   if (ws_bytes < need)
     return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
-  HT_HIP(hipSetDevice(ctx->device));
-  return run_plan(ctx, M, reinterpret_cast<hipStream_t>(stream));
+  void* table = nullptr;
+  if (!M.table.empty()) {
+    HT_HIP(hipMalloc(&table, M.table.size()));
+    HT_HIP(hipMemcpy(table, M.table.data(), M.table.size(), hipMemcpyHostToDevice));
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->btable) {
+    HT_HIP(hipDeviceSynchronize());   // the previous table may still be read by queued launches
+    (void)hipFree(ctx->btable);
+  }
+  M.table.clear();
+  M.table.shrink_to_fit();
+  ctx->bsig.swap(sig);
+  ctx->bplan = std::move(M);
+  ctx->btable = table;
+  return launch_plan(ctx, ctx->bplan, table, reinterpret_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------------ orthogonalisation
