@@ -960,9 +960,13 @@ struct OrthOut {
   GlobalState* st = nullptr;
 };
 
+// overlap: each level's orthogonal factor Qo (read only by the Gramian pass)
+// is formed on the second stream while the next level's first Cholesky step
+// (a few workgroups) leaves the chip idle; the caller's stream waits for it
+// at the end.
 void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, OrthOut& O,
                const std::vector<int>& rcap, bool need_proj_bufs, const ht_desc* out,
-               const ht_desc* inplace) {
+               const ht_desc* inplace, bool overlap = false) {
   const int nn = tr.nn, d = tr.d;
   // Precision policy.  The first CholeskyQR2 sweeps (leaf frames and M_{2,3}
   // of every transfer tensor) run on the FP32 matrix cores in the mixed path:
@@ -1164,6 +1168,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     add_combine(leaves, a);
   }
   // inner nodes by height
+  bool forked = false;
+  std::vector<GemmDesc> pending_dq;
   const int H = tr.height[0];
   for (int h = 1; h < H; ++h) {
     std::vector<int> nodes;
@@ -1219,6 +1225,15 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     bool rk_all = !dg.empty();
     for (const auto& g : dg) rk_all = rk_all && rk_shape(g) && rk_gram(g);
     add_gemm(P, dg, T, T, F64, rk_all ? MATH_F64 : smath, GEMM_ATOMIC, true, true);
+    if (!pending_dq.empty()) {   // the previous level's Qo beside this level's Cholesky
+      g_label = "inner_orth_factor";
+      add_sync(P, OP_FORK);
+      g_stream = 1;
+      add_gemm(P, pending_dq, F64, T, T, MATH_F64, GEMM_STORE, false, false);
+      g_stream = 0;
+      pending_dq.clear();
+      forked = true;
+    }
     {
       g_label = "inner_chol1";
       auto a = small_args(nodes, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
@@ -1262,7 +1277,14 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       add_combine(nodes, a);
     }
     g_label = "inner_orth_factor";
-    add_gemm(P, dq, F64, T, inplace ? inplace->transfer_dtype : T, MATH_F64, GEMM_STORE, false, false);
+    if (overlap)
+      pending_dq = dq;   // formed during the next level
+    else
+      add_gemm(P, dq, F64, T, inplace ? inplace->transfer_dtype : T, MATH_F64, GEMM_STORE, false, false);
+  }
+  if (!pending_dq.empty()) {   // the top level's Qo
+    g_label = "inner_orth_factor";
+    add_gemm(P, pending_dq, F64, T, T, MATH_F64, GEMM_STORE, false, false);
   }
   g_label = "root_orth";
   // root: HD = blockdiag(alpha_c B_D^(c)); BDo = R_t1 HD R_t2^T
@@ -1298,6 +1320,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     a2.push_back(h);
     add_gemm(P, a2, F64, F64, F64, MATH_F64, GEMM_STORE, true, true);
   }
+  if (forked) add_sync(P, OP_JOIN);
   (void)out;
 }
 
@@ -1485,7 +1508,7 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
   const int tsz = esize(T);
   Arena A(ws);
   OrthOut O;
-  plan_orth(P, tr, S, prec, A, O, rcap, true, out, nullptr);
+  plan_orth(P, tr, S, prec, A, O, rcap, true, out, nullptr, overlap);
   std::vector<const void*> Qo(nn, nullptr);
   for (int t = 1; t < nn; ++t) Qo[t] = O.nb[t].Qo;
   // Node groups.  An eigensolver launch lasts as long as one node's
@@ -2378,7 +2401,9 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
   bool forked = false;   // second-stream launches only between a fork and its join
   for (const auto& op : P.ops) {
     if (op.kind == OP_FORK || op.kind == OP_JOIN) {
-      if (forked != (op.kind == OP_JOIN)) return fail(HT_EINVAL, "validator: unbalanced fork / join");
+      // a fork may follow a fork (the second stream waits again); a join
+      // closes them all
+      if (op.kind == OP_JOIN && !forked) return fail(HT_EINVAL, "validator: join without a fork");
       forked = op.kind == OP_FORK;
       ++opi;
       continue;
