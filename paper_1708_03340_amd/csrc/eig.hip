@@ -265,6 +265,13 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           d_i1 = d_i;
           return true;
         };
+        // Rotation u of a block consumes the operands (eb[u], db[u]) and at
+        // once loads those of rotation u of the next block into the same
+        // registers, so the loop carries no copies.  A block that meets
+        // x2 = 0 ends with g and p not finite (the reciprocal square root of
+        // zero turns every later quantity into NaN); it is redone rotation by
+        // rotation from its operands in LDS, unchanged until its results are
+        // stored.
         double eb[8], db[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -274,21 +281,12 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
         }
         int i0 = m - 1;
         while (i0 - 7 >= l) {
-          double en[8], dn[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int idx = max(i0 - 8 - u, l);
-            en[u] = eo[idx];
-            dn[u] = dg[idx];
-          }
           const double sn0 = sn, cs0 = cs, p0 = p, g0 = g, d0 = d_i1;
           double oe[8], od[8], oc[8], os[8];
-          bool zero = false;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const double f = sn * eb[u], bb = cs * eb[u];
             const double x2 = f * f + g * g;
-            zero = zero || x2 == 0.0;
             const double ir = rsqrt3(x2);
             oe[u] = x2 * ir;
             sn = f * ir;
@@ -301,8 +299,11 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
             oc[u] = cs;
             os[u] = sn;
             d_i1 = db[u];
+            const int idx = max(i0 - 8 - u, l);
+            eb[u] = eo[idx];
+            db[u] = dg[idx];
           }
-          if (!zero) {
+          if (isfinite(g) && isfinite(p)) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const int i = i0 - u;
@@ -313,13 +314,8 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
             }
           } else {   // redo the block rotation by rotation
             sn = sn0; cs = cs0; p = p0; g = g0; d_i1 = d0;
-            for (int u = 0; u < 8 && !split; ++u) split = !step(i0 - u, eb[u], db[u]);
+            for (int u = 0; u < 8 && !split; ++u) split = !step(i0 - u, eo[i0 - u], dg[i0 - u]);
             if (split) break;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            eb[u] = en[u];
-            db[u] = dn[u];
           }
           i0 -= 8;
         }
