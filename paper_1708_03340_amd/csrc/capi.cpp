@@ -73,7 +73,7 @@ namespace {
 
 enum OpKind : int {
   OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
-  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_FINISHR,
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH,
   OP_FORK,   // the library's second stream waits for the caller's stream here
   OP_JOIN    // the caller's stream waits for everything on the second stream
 };
@@ -313,9 +313,11 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
     const double k3 = (double)x.K * x.K * x.K;
     // operation counts: symmetric eigensolver with vectors (Householder
     // tridiagonalisation 4/3 K^3, implicit QL with vectors about 6 K^3,
-    // back-transformation 2 K^3); Cholesky K^3/3 and triangular inverse K^3/3
+    // back-transformation 2 K^3); Cholesky K^3/3 and triangular inverse K^3/3,
+    // and in the second step the two triangular products, K^3/3 each
     if (kind == OP_EIG) op.flops += (4.0 / 3.0 + 8.0) * k3;
     if (kind == OP_CHOL1 || kind == OP_CHOL2) op.flops += 2.0 / 3.0 * k3;
+    if (kind == OP_CHOL2) op.flops += 2.0 / 3.0 * k3;
   }
   op.toff = put(P, a);
   op.count = (int)a.size();
@@ -503,7 +505,7 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
         }
         break;
       }
-      case OP_CHOL1: case OP_CHOL2: case OP_FINISHR: case OP_EIG: case OP_PROJPREP: case OP_RANK: {
+      case OP_CHOL1: case OP_CHOL2: case OP_EIG: case OP_PROJPREP: case OP_RANK: {
         std::vector<SmallArgs> sa;
         std::vector<StateRec> sr;
         Op op = o0;
@@ -736,10 +738,6 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
         e = launch_chol(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count,
                         op.kind == OP_CHOL1 ? 1 : 2, stream, reinterpret_cast<GlobalState*>(op.p0));
         break;
-      case OP_FINISHR:
-        e = launch_finish_r(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, stream,
-                            reinterpret_cast<GlobalState*>(op.p0));
-        break;
       case OP_EIG:
         e = launch_eig(reinterpret_cast<const SmallArgs*>(tb + op.toff), op.count, op.i0, stream,
                        reinterpret_cast<GlobalState*>(op.p0));
@@ -818,7 +816,6 @@ std::string kernel_name(const Op& op) {
              (op.g.math == MATH_F32 ? "float" : "double") + "," +
              (op.g.math == MATH_F32 && op.g.acc64 ? "true" : "false") + ">";
     case OP_CHOL1: case OP_CHOL2: return "chol_kernel";
-    case OP_FINISHR: return "finish_r_kernel";
     case OP_EIG: return op.i0 <= 64 ? "eig_kernel<64>" : (op.i0 <= 96 ? "eig_kernel<96>" : "eig_kernel<128>");
     case OP_RANK: return "rank_kernel";
     case OP_PROJPREP: return "proj_prep_kernel";
@@ -889,8 +886,7 @@ struct Arena {
 // Per-node buffers of the truncation / orthogonalisation.
 struct NodeBufs {
   int K = 0, rcap = 0;
-  double *G = nullptr, *G2 = nullptr, *Bh = nullptr, *R1 = nullptr, *Ri1 = nullptr, *R2 = nullptr,
-         *R2i = nullptr, *R = nullptr,
+  double *G = nullptr, *G2 = nullptr, *Bh = nullptr, *R1 = nullptr, *Ri1 = nullptr, *R = nullptr,
          *Ri = nullptr, *Q = nullptr, *lam = nullptr, *Qm = nullptr, *scratch = nullptr;
   void *Rf = nullptr, *QmT = nullptr, *Pm = nullptr;
   int32_t* rank = nullptr;
@@ -1003,8 +999,6 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     b.rcap = rcap.empty() ? b.K : rcap[t];
     b.R1 = (double*)A.take(kk * 8);
     b.Ri1 = (double*)A.take(kk * 8);
-    b.R2 = (double*)A.take(kk * 8);
-    b.R2i = (double*)A.take(kk * 8);
     b.R = (double*)A.take(kk * 8);
     b.Ri = (double*)A.take(kk * 8);
     b.Rf = A.take(kk * tsz);
@@ -1076,30 +1070,6 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     }
     add_gemm(P, ds, fdt, fdt, F64, smath, GEMM_ATOMIC, true, true);
   }
-  // second CholeskyQR2 step: R = R2 R1 and R^{-1} = R1^{-1} R2^{-1} (FP64
-  // GEMMs), then R is normalised by a power of two
-  auto add_combine = [&](const std::vector<int>& nodes, const std::vector<SmallArgs>& a) {
-    std::vector<GemmDesc> dr, di;
-    for (int t : nodes) {
-      const NodeBufs& b = O.nb[t];
-      GemmDesc g = blank_desc();
-      g.A = b.R2; g.sAm = b.K; g.sAk = 1;
-      g.B = b.R1; g.sBk = b.K; g.sBn = 1;
-      g.C = b.R; g.sCm = b.K; g.sCn = 1;
-      g.M = g.N = g.K = b.K;
-      dr.push_back(g);
-      GemmDesc h = blank_desc();
-      h.A = b.Ri1; h.sAm = b.K; h.sAk = 1;
-      h.B = b.R2i; h.sBk = b.K; h.sBn = 1;
-      h.C = b.Ri; h.sCm = b.K; h.sCn = 1;
-      h.M = h.N = h.K = b.K;
-      di.push_back(h);
-    }
-    add_gemm(P, dr, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
-    add_gemm(P, di, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
-    add_small(P, OP_FINISHR, a);
-    P.ops.back().p0 = O.st;
-  };
   auto small_args = [&](const std::vector<int>& nodes, double tol) {
     std::vector<SmallArgs> v;
     for (int t : nodes) {
@@ -1107,7 +1077,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       SmallArgs a;
       std::memset(&a, 0, sizeof(a));
       a.K = b.K; a.node = t; a.rcap = b.rcap;
-      a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1; a.R2 = b.R2; a.R2i = b.R2i;
+      a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1;
       a.R = b.R; a.Ri = b.Ri; a.Rf = b.Rf;
       a.rf_type = T; a.tol_rel = tol;
       a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rank_dev = b.rank; a.scratch = b.scratch;
@@ -1163,9 +1133,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   {
     g_label = "leaf_chol2";
     auto a = small_args(leaves, 1e-13);
-    add_small(P, OP_CHOL2, a);
+    add_small(P, OP_CHOL2, a);   // also R = R2 R1, Ri = R1^{-1} R2^{-1}, Rf
     P.ops.back().p0 = O.st;
-    add_combine(leaves, a);
   }
   // inner nodes by height
   bool forked = false;
@@ -1272,9 +1241,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     {
       g_label = "inner_chol2";
       auto a = small_args(nodes, 1e-13);
-      add_small(P, OP_CHOL2, a);
+      add_small(P, OP_CHOL2, a);   // also R = R2 R1, Ri = R1^{-1} R2^{-1}, Rf
       P.ops.back().p0 = O.st;
-      add_combine(nodes, a);
     }
     g_label = "inner_orth_factor";
     if (overlap)
@@ -2452,14 +2420,6 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (s) return s;
         if (g.alpha_dev) { s = check_range(g.alpha_dev, 0, 0, 8, w + " alpha"); if (s) return s; }
       }
-    } else if (op.kind == OP_FINISHR) {
-      const SmallArgs* as = reinterpret_cast<const SmallArgs*>(at(op.toff));
-      for (int i = 0; i < op.count; ++i) {
-        const int64_t kk = (int64_t)as[i].K * as[i].K;
-        if ((s = check_range(as[i].R, 0, kk - 1, 8, tag + " R")) ||
-            (s = check_range(as[i].Rf, 0, kk - 1, esize(as[i].rf_type), tag + " Rf")))
-          return s;
-      }
     } else if (op.kind == OP_CHOL1 || op.kind == OP_CHOL2 || op.kind == OP_EIG || op.kind == OP_RANK ||
                op.kind == OP_PROJPREP || op.kind == OP_SIGMA) {
       const SmallArgs* as = reinterpret_cast<const SmallArgs*>(at(op.toff));
@@ -2475,7 +2435,8 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
           if ((s = chk(a.G, kk, 8, "G")) || (s = chk(a.G2, kk, 8, "G2")) || (s = chk(a.R1, kk, 8, "R1")) ||
               (s = chk(a.Ri1, kk, 8, "Ri1")))
             return s;
-          if (op.kind == OP_CHOL2 && ((s = chk(a.R2, kk, 8, "R2")) || (s = chk(a.R2i, kk, 8, "R2i"))))
+          if (op.kind == OP_CHOL2 && ((s = chk(a.R, kk, 8, "R")) || (s = chk(a.Ri, kk, 8, "Ri")) ||
+                                      (s = chk(a.Rf, kk, esize(a.rf_type), "Rf"))))
             return s;
         } else if (op.kind == OP_EIG) {
           if ((s = chk(a.Bh, kk, 8, "Bh")) || (s = chk(a.Q, kk, 8, "Q")) || (s = chk(a.lam, a.K, 8, "lam")) ||

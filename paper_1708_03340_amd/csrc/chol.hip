@@ -17,6 +17,12 @@
 // spread over the four waves.  R^{-1} is then formed by blocked back
 // substitution, X_pq = -X_pp sum_{k=p+1..q} R_pk X_kq, also on MFMA.  A
 // dropped row is a zero row of R and a unit row of the matrix inverted.
+//
+// Sweep 2 ends with the step's combination, R = R2 R1 and
+// R^{-1} = R1^{-1} R2^{-1} (products of block upper-triangular matrices on
+// MFMA, R2 and R2^{-1} from LDS, R1 and R1^{-1} from global memory), and
+// normalises R by 2^-e, e the binary exponent of max |R|; e is added to the
+// tensor's scale exponent and Rf receives R in the forward-product type.
 #include "dense_util.h"
 
 namespace ht {
@@ -33,7 +39,8 @@ __device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) {
 }
 
 // sweep 1: G -> R1, Ri1 = R1^{-1}.  sweep 2: G2 -> R2 (rows of vanishing
-// pivots dropped), R2i = inverse of R2 with unit diagonal on dropped rows.
+// pivots dropped) and R2^{-1} (unit diagonal on dropped rows), kept in LDS,
+// then R, Ri and Rf as above.
 __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ args, int sweep,
                                                   GlobalState* st) {
   __shared__ double L[KMAX * LDL];            // A, then R (upper blocks) and X^T (lower blocks)
@@ -204,14 +211,13 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     __syncthreads();
   }
 
-  // ---- R out (upper blocks of L; zero below the diagonal)
-  double* Rout = sweep == 1 ? a.R1 : a.R2;
-  double* Riout = sweep == 1 ? a.Ri1 : a.R2i;
-  for (int r = wave; r < K; r += NT / 64)
-    for (int c = lane; c < K; c += 64) {
-      const double lv = L[r * LDL + c];
-      gst(&Rout[r * K + c], lv * (c >= r ? 1.0 : 0.0));
-    }
+  // ---- R1 out (upper blocks of L; zero below the diagonal)
+  if (sweep == 1)
+    for (int r = wave; r < K; r += NT / 64)
+      for (int c = lane; c < K; c += 64) {
+        const double lv = L[r * LDL + c];
+        gst(&a.R1[r * K + c], lv * (c >= r ? 1.0 : 0.0));
+      }
   __syncthreads();   // the lower blocks of L are overwritten below
 
   // ---- X = R^{-1} by blocked back substitution; X_pq (p < q) is kept
@@ -238,31 +244,99 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     }
     __syncthreads();
   }
-  for (int r = wave; r < K; r += NT / 64)
-    for (int c = lane; c < K; c += 64) {
-      const int pr = r >> 4, pc = c >> 4;
-      const double xd = Xd[pr][(r & 15) * LDD + (c & 15)], lv = L[c * LDL + r];
-      gst(&Riout[r * K + c], xd * (pr == pc ? 1.0 : 0.0) + lv * (pr < pc ? 1.0 : 0.0));
-    }
-  if (sweep == 2 && any && tid == 0) atomicOr(&st->flags, 1u);
-}
+  if (sweep == 1) {
+    for (int r = wave; r < K; r += NT / 64)
+      for (int c = lane; c < K; c += 64) {
+        const int pr = r >> 4, pc = c >> 4;
+        const double xd = Xd[pr][(r & 15) * LDD + (c & 15)], lv = L[c * LDL + r];
+        gst(&a.Ri1[r * K + c], xd * (pr == pc ? 1.0 : 0.0) + lv * (pr < pc ? 1.0 : 0.0));
+      }
+    return;
+  }
+  if (any && tid == 0) atomicOr(&st->flags, 1u);
 
-// R (= R2 R1, formed by a GEMM) is divided by 2^e, e the binary exponent of
-// max |R|; e is added to the scale exponent; Rf = R in the forward type.
-__global__ __launch_bounds__(NT) void finish_r_kernel(const SmallArgs* __restrict__ args, GlobalState* st) {
-  __shared__ double red[NT / 64];
-  const SmallArgs& a = args[blockIdx.x];
-  if (a.st) st = a.st;
-  const int K = a.K;
-  const int tid = threadIdx.x;
+  // ---- sweep 2: R = R2 R1 and Ri = R1^{-1} R2^{-1}.  Upper block (p, q),
+  // p <= q, numbered row by row, is formed by wave (number mod 4):
+  // R_pq = sum_{k=p..q} R2_pk R1_kq, Ri_pq = sum_{k=p..q} Ri1_pk X_kq.  The
+  // global operands of a block are loaded together (clamped addresses,
+  // masked values); blocks past q load but do not multiply.
+  const int nblk = NB * (NB + 1) / 2;
+  constexpr int MAXJ = (KMAX / 16) * (KMAX / 16 + 1) / 2 / (NT / 64);   // blocks per wave
+  doublex4 racc[MAXJ];
   double mx = 0.0;
-  for (int i = tid; i < K * K; i += NT) mx = fmax(mx, fabs(a.R[i]));
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) {
+    racc[j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const int idx = wave + (NT / 64) * j;
+    if (idx >= nblk) continue;
+    int p = 0, rem = idx;
+    while (rem >= NB - p) {
+      rem -= NB - p;
+      ++p;
+    }
+    const int q = p + rem;
+    double b1[KMAX / 16][4], a1[KMAX / 16][4];
+#pragma unroll
+    for (int t = 0; t < KMAX / 16; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kr = 16 * (p + t) + 4 * s + l4;   // row of R1, column of Ri1
+        const int c = 16 * q + l16, r = 16 * p + l16;
+        const bool okb = kr < K && c < K, oka = r < K && kr < K;
+        b1[t][s] = gld(&a.R1[min(kr, K - 1) * K + min(c, K - 1)]) * (okb ? 1.0 : 0.0);
+        a1[t][s] = gld(&a.Ri1[min(r, K - 1) * K + min(kr, K - 1)]) * (oka ? 1.0 : 0.0);
+      }
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0}, iacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < KMAX / 16; ++t) {
+      const int k = p + t;
+      if (k > q) break;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + l4;
+        const double r2 = L[(16 * p + l16) * LDL + 16 * k + kk] * ((k > p || kk >= l16) ? 1.0 : 0.0);
+        acc = mfma(r2, b1[t][s], acc);
+        const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
+        iacc = mfma(a1[t][s], xb, iacc);
+      }
+    }
+    racc[j] = acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+      if (r < K && c < K) gst(&a.Ri[r * K + c], iacc[v]);
+      mx = fmax(mx, fabs(acc[v]));
+    }
+  }
+  // blocks below the diagonal are zero
+  for (int r = wave; r < K; r += NT / 64)
+    for (int c = lane; c < (r & ~15); c += 64) {
+      gst(&a.R[r * K + c], 0.0);
+      gst(&a.Ri[r * K + c], 0.0);
+      if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[r * K + c] = 0.0f;
+      else reinterpret_cast<double*>(a.Rf)[r * K + c] = 0.0;
+    }
   const int e = exp2_of(wg_max(mx, red));
-  for (int i = tid; i < K * K; i += NT) {
-    const double v = ldexp(a.R[i], -e);
-    a.R[i] = v;
-    if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[i] = (float)v;
-    else reinterpret_cast<double*>(a.Rf)[i] = v;
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) {
+    const int idx = wave + (NT / 64) * j;
+    if (idx >= nblk) continue;
+    int p = 0, rem = idx;
+    while (rem >= NB - p) {
+      rem -= NB - p;
+      ++p;
+    }
+    const int q = p + rem;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+      if (r < K && c < K) {
+        const double x = ldexp(racc[j][v], -e);
+        gst(&a.R[r * K + c], x);
+        if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[r * K + c] = (float)x;
+        else reinterpret_cast<double*>(a.Rf)[r * K + c] = x;
+      }
+    }
   }
   if (tid == 0 && e != 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->log2_scale), (unsigned long long)(long long)e);
@@ -276,10 +350,5 @@ hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, G
   return hipGetLastError();
 }
 
-hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finish_r_kernel, dim3(n), dim3(NT), 0, s, args, st);
-  return hipGetLastError();
-}
 
 }  // namespace ht

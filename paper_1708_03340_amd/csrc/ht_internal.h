@@ -107,9 +107,7 @@ struct SmallArgs {
   double* G2;              // K x K second-sweep Gram
   double* R1;              // K x K first-sweep factor
   double* Ri1;             // K x K inverse of the first-sweep factor
-  double* R2;              // K x K second-sweep factor
-  double* R2i;             // K x K its inverse (unit diagonal on dropped rows)
-  double* R;               // K x K upper factor (output, normalised by 2^-e)
+  double* R;               // K x K upper factor R2 R1 (output, normalised by 2^-e)
   double* Ri;              // K x K inverse of the unnormalised factor
   double tol_rel;          // pivot tolerance relative to the largest diagonal entry
   void* Rf;                // K x K copy of R in the forward-product type
@@ -164,7 +162,6 @@ struct CopyRec {
 hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s);
 hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);
-hipError_t launch_finish_r(const SmallArgs* args, int n, hipStream_t s, GlobalState* st);
 // max_k: the largest K among the args (picks the instantiation)
 hipError_t launch_eig(const SmallArgs* args, int n, int max_k, hipStream_t s, GlobalState* st);
 hipError_t launch_rank_select(const SmallArgs* args, const StateRec* r, int n, hipStream_t s);
