@@ -259,7 +259,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   // p <= q, numbered row by row, is formed by wave (number mod 4):
   // R_pq = sum_{k=p..q} R2_pk R1_kq, Ri_pq = sum_{k=p..q} Ri1_pk X_kq.  The
   // global operands of a block are loaded together (clamped addresses,
-  // masked values); blocks past q load but do not multiply.
+  // masked values) before its products.
   const int nblk = NB * (NB + 1) / 2;
   constexpr int MAXJ = (KMAX / 16) * (KMAX / 16 + 1) / 2 / (NT / 64);   // blocks per wave
   doublex4 racc[MAXJ];
@@ -277,7 +277,8 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     const int q = p + rem;
     double b1[KMAX / 16][4], a1[KMAX / 16][4];
 #pragma unroll
-    for (int t = 0; t < KMAX / 16; ++t)
+    for (int t = 0; t < KMAX / 16; ++t) {
+      if (p + t > q) break;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kr = 16 * (p + t) + 4 * s + l4;   // row of R1, column of Ri1
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         b1[t][s] = gld(&a.R1[min(kr, K - 1) * K + min(c, K - 1)]) * (okb ? 1.0 : 0.0);
         a1[t][s] = gld(&a.Ri1[min(r, K - 1) * K + min(kr, K - 1)]) * (oka ? 1.0 : 0.0);
       }
+    }
     doublex4 acc = {0.0, 0.0, 0.0, 0.0}, iacc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < KMAX / 16; ++t) {

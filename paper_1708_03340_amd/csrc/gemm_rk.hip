@@ -15,7 +15,10 @@
 // of the same matrix, or a son Gramian, which inherits the symmetry of
 // Bhat_t) only the 36 blocks of 16 x 16 on or above the diagonal are formed,
 // each wave taking the nine blocks of block rows w and 7-w, and the
-// off-diagonal blocks are added at both places.
+// off-diagonal blocks are added at both places.  A son Gramian whose operands
+// are both contiguous along their row index stages its chunks k-major (a
+// chunk row holds 128 consecutive rows): each load instruction then reads
+// 512 contiguous bytes and each LDS write covers all banks once.
 #include "ht_internal.h"
 
 namespace ht {
@@ -44,7 +47,7 @@ template <> struct RkTraits<float> {
 
 // MODE 0: full result; 1: Gram matrix (B = A^T, upper blocks); 2: separate B
 // but a symmetric result (upper blocks, mirrored), as for the son Gramians
-template <typename TA, typename TB, typename TM, int MODE, int RK_KC>
+template <typename TA, typename TB, typename TM, int MODE, int RK_KC, bool KM = false>
 __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const GemmDesc* __restrict__ descs,
                                                                         int nsplit, int tC, int mode) {
   constexpr bool SYM = MODE != 0;      // upper blocks only
@@ -55,6 +58,13 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   constexpr int LDK = RK_KC + Tr::PAD;
   __shared__ TM As[2][128][LDK];
   __shared__ TM Bs[SAMEB ? 1 : 2][SAMEB ? 1 : 128][LDK];
+  // KM: both operands contiguous along their row index, staged k-major
+  // (chunk row k holds 128 consecutive rows), written and read without
+  // bank conflicts
+  static_assert(!KM || (MODE == 2 && RK_KC * 128 <= 128 * LDK), "k-major staging");
+  TM (*const Ak)[128] = reinterpret_cast<TM (*)[128]>(&As[0][0][0]);   // [buf * RK_KC + k][r]
+  TM (*const Bk)[128] = reinterpret_cast<TM (*)[128]>(&Bs[0][0][0]);
+  constexpr int KMB = (128 * LDK) / 128;   // k rows per buffer in the k-major view
 
   const GemmDesc& D = descs[blockIdx.y];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -76,6 +86,20 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   auto load = [&](int c) {
     const int kb = c / cpb, k0 = (c % cpb) * RK_KC;
     const TA* Ak = Ab + (int64_t)kb * D.sAkb;
+    if constexpr (KM) {   // thread t: row t % 128, k from (t / 128) * LU
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int r = tid & 127, k = k0 + (tid >> 7) * LU + u;
+        ra[u] = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]) * (TM)(k < K);
+      }
+      const TB* Bk = Bb + (int64_t)kb * D.sBkb;
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int n = tid & 127, k = k0 + (tid >> 7) * LU + u;
+        rb[u] = (TM)gld(&Bk[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]) * (TM)(k < K);
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
       const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
@@ -95,6 +119,14 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
     }
   };
   auto stash = [&](int buf) {
+    if constexpr (KM) {
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        Ak[buf * KMB + (tid >> 7) * LU + u][tid & 127] = ra[u];
+        Bk[buf * KMB + (tid >> 7) * LU + u][tid & 127] = rb[u];
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
       const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
@@ -215,15 +247,32 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
         const int kq = 16 * st + 4 * (lane >> 4);
 #pragma unroll
         for (int hq = 0; hq < 2; ++hq) {
-          const TM* pa0 = &As[buf][16 * wave + (lane & 15)][kq + 2 * hq];
-          const TM* pa1 = &As[buf][16 * (7 - wave) + (lane & 15)][kq + 2 * hq];
-          const TM fa0[2] = {pa0[0], pa0[1]}, fa1[2] = {pa1[0], pa1[1]};
+          TM fa0[2], fa1[2];
+          if constexpr (KM) {
+            const int kr = buf * KMB + kq + 2 * hq;
+            fa0[0] = Ak[kr][16 * wave + (lane & 15)];
+            fa0[1] = Ak[kr + 1][16 * wave + (lane & 15)];
+            fa1[0] = Ak[kr][16 * (7 - wave) + (lane & 15)];
+            fa1[1] = Ak[kr + 1][16 * (7 - wave) + (lane & 15)];
+          } else {
+            const TM* pa0 = &As[buf][16 * wave + (lane & 15)][kq + 2 * hq];
+            const TM* pa1 = &As[buf][16 * (7 - wave) + (lane & 15)][kq + 2 * hq];
+            fa0[0] = pa0[0]; fa0[1] = pa0[1]; fa1[0] = pa1[0]; fa1[1] = pa1[1];
+          }
 #pragma unroll
           for (int bl = 0; bl < 9; ++bl) {
             const int col = bcol(bl);
-            const TM* pb = SAMEB ? &As[buf][16 * col + (lane & 15)][kq + 2 * hq]
-                                 : &Bs[buf][16 * col + (lane & 15)][kq + 2 * hq];
-            const TM fb0 = pb[0], fb1 = pb[1];
+            TM fb0, fb1;
+            if constexpr (KM) {
+              const int kr = buf * KMB + kq + 2 * hq;
+              fb0 = Bk[kr][16 * col + (lane & 15)];
+              fb1 = Bk[kr + 1][16 * col + (lane & 15)];
+            } else {
+              const TM* pb = SAMEB ? &As[buf][16 * col + (lane & 15)][kq + 2 * hq]
+                                   : &Bs[buf][16 * col + (lane & 15)][kq + 2 * hq];
+              fb0 = pb[0];
+              fb1 = pb[1];
+            }
             const bool first = bl < nfirst;
             acc[bl] = Tr::mfma(first ? fa0[0] : fa1[0], fb0, acc[bl]);
             acc[bl] = Tr::mfma(first ? fa0[1] : fa1[1], fb1, acc[bl]);
@@ -307,6 +356,9 @@ hipError_t go_rk(const GemmLaunch& g, hipStream_t s) {
   if (g.rk_sym == 1)
     hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 1, 32>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
                        g.mode);
+  else if (g.rk_sym == 2 && !g.a_kcontig && !g.b_kcontig)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16, true>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
   else if (g.rk_sym == 2)
     hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
                        g.mode);
