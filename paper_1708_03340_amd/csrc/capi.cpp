@@ -249,10 +249,8 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
       op.g.rk = true;
       op.g.rk_sym = sym ? 1 : 2;
       op.g.rk_kc = sym ? 32 : 16;
-      // split-K width: about 1024 workgroups for a Gram matrix, 512 (one
-      // round at two per CU) for a son Gramian
-      const long long target = sym ? 1024 : 512;
-      const long long want = (target + (long long)descs.size() - 1) / (long long)descs.size();
+      // split-K width: about 512 workgroups, one round at two per CU
+      const long long want = (512 + (long long)descs.size() - 1) / (long long)descs.size();
       op.g.rk_split = (int)std::max<long long>(1, std::min(want, (chunks + 15) / 16));
       big = false;
     }
