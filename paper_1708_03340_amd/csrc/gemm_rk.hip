@@ -79,9 +79,11 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   const TA* Ab = reinterpret_cast<const TA*>(D.A);
   const TB* Bb = reinterpret_cast<const TB*>(D.B);
 
-  // loader coordinates: along k (thread t: row t/2, k (t%2)*LU .. +LU-1) or
-  // along the row index (thread t: k t/(128/LU), LU rows from (t%(128/LU))*LU)
+  // loader coordinates: along k (thread t: k t % KC of rows t / KC + (256 / KC) u,
+  // so that KC consecutive lanes read one row's chunk and write one LDS row)
+  // or along the row index (thread t: k t/(128/LU), LU rows from (t%(128/LU))*LU)
   constexpr int RG = 128 / LU;
+  constexpr int KR = 256 / RK_KC;   // rows per pass of the k-contiguous loader
   TM ra[LU], rb[LU];
   auto load = [&](int c) {
     const int kb = c / cpb, k0 = (c % cpb) * RK_KC;
@@ -102,8 +104,8 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
-      const int k = a_kc ? k0 + (tid & 1) * LU + u : k0 + tid / RG;
+      const int r = a_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
+      const int k = a_kc ? k0 + tid % RK_KC : k0 + tid / RG;
       const TM v = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]);
       ra[u] = v * (TM)(k < K);
     }
@@ -111,8 +113,8 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
       const TB* Bk = Bb + (int64_t)kb * D.sBkb;
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
-        const int n = b_kc ? (tid >> 1) : (tid % RG) * LU + u;
-        const int k = b_kc ? k0 + (tid & 1) * LU + u : k0 + tid / RG;
+        const int n = b_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
+        const int k = b_kc ? k0 + tid % RK_KC : k0 + tid / RG;
         const TM v = (TM)gld(&Bk[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]);
         rb[u] = v * (TM)(k < K);
       }
@@ -129,15 +131,15 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int r = a_kc ? (tid >> 1) : (tid % RG) * LU + u;
-      const int k = a_kc ? (tid & 1) * LU + u : tid / RG;
+      const int r = a_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
+      const int k = a_kc ? tid % RK_KC : tid / RG;
       As[buf][r][k] = ra[u];
     }
     if (!SAMEB) {
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
-        const int n = b_kc ? (tid >> 1) : (tid % RG) * LU + u;
-        const int k = b_kc ? (tid & 1) * LU + u : tid / RG;
+        const int n = b_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
+        const int k = b_kc ? tid % RK_KC : tid / RG;
         Bs[buf][n][k] = rb[u];
       }
     }
