@@ -1053,11 +1053,31 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
 
   const int fdt = X0.frame_dtype, tdt = X0.transfer_dtype;
   g_label = "leaf_gram_sweep1";
-  // leaves: sweep 1 Gram G = W^T W (blocks of summand pairs)
+  // leaves: sweep 1 Gram G = W^T W.  Two frames with one row stride form one
+  // float64 Gram matrix of the split-K kernel (rows of the second frame at a
+  // fixed element offset); otherwise the Gram matrix is formed in blocks of
+  // summand pairs.
   {
-    std::vector<GemmDesc> ds;
+    std::vector<GemmDesc> ds, dw;
+    const int64_t es = esize(fdt);
     for (int mu = 0; mu < d; ++mu) {
       const int t = tr.leaf_node[mu];
+      if (S.n_in == 2) {
+        const int r0 = S.X[0]->rank[t], r1 = S.X[1]->rank[t];
+        const int64_t ld = S.X[0]->leaf_ld[mu];
+        const int64_t diff = (int64_t)((const char*)S.X[1]->leaf[mu] - (const char*)S.X[0]->leaf[mu]);
+        GemmDesc g = blank_desc();
+        g.A = S.X[0]->leaf[mu]; g.sAm = ld; g.sAk = 1;
+        g.B = g.A; g.sBk = 1; g.sBn = ld;
+        g.a2off = diff / es - (int64_t)r0 * ld; g.msplit = r0;
+        g.C = O.nb[t].G; g.sCm = S.K[t]; g.sCn = 1;
+        g.M = g.N = r0 + r1; g.K = (int)X0.n[mu];
+        if (S.X[1]->leaf_ld[mu] == ld && diff % es == 0 && r0 > 0 && r1 > 0 && S.off[t][1] == r0 &&
+            S.K[t] == r0 + r1 && rk_shape(g) && rk_gram(g)) {
+          dw.push_back(g);
+          continue;
+        }
+      }
       for (int c1 = 0; c1 < S.n_in; ++c1)
         for (int c2 = 0; c2 < S.n_in; ++c2) {
           GemmDesc g = blank_desc();
@@ -1069,6 +1089,8 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
           ds.push_back(g);
         }
     }
+    // float64 MFMA: as fast here as float32, and exact products
+    add_gemm(P, dw, fdt, fdt, F64, MATH_F64, GEMM_ATOMIC, true, true);
     add_gemm(P, ds, fdt, fdt, F64, smath, GEMM_ATOMIC, true, true);
   }
   auto small_args = [&](const std::vector<int>& nodes, double tol) {
@@ -2396,6 +2418,21 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
           for (int sg = 0; sg < nseg; ++sg) kt += g.nseg > 0 ? g.segK[sg] : g.K;
           if (g.KB != 1 || kt < 1 || kt > 128 || (op.g.sb_swap ? g.N : g.M) > 128)
             return fail(HT_EINVAL, "validator: streamed GEMM shape " + w);
+        }
+        if (g.msplit > 0) {   // two frames side by side: split-K Gram launches only
+          if (!op.g.rk || op.g.rk_sym != 1 || g.kr || g.nseg > 0 || g.nbatch != 1 || g.msplit >= g.M || g.A != g.B)
+            return fail(HT_EINVAL, "validator: split rows outside a Gram launch " + w);
+          for (int sg = 0; sg < g.KB; ++sg) {
+            const int64_t k0 = (int64_t)sg * g.sAkb, kl = (int64_t)(g.K - 1) * g.sAk;
+            s = check_range(g.A, k0, k0 + (int64_t)(g.msplit - 1) * g.sAm + kl, ea, w + " A rows below the split");
+            if (!s)
+              s = check_range(g.A, k0 + (int64_t)g.msplit * g.sAm + g.a2off,
+                              k0 + (int64_t)(g.M - 1) * g.sAm + g.a2off + kl, ea, w + " A rows from the split");
+            if (s) return s;
+          }
+          s = check_range(g.C, 0, (int64_t)(g.M - 1) * g.sCm + (int64_t)(g.N - 1) * g.sCn, ec, w + " C");
+          if (s) return s;
+          continue;
         }
         for (int sg = 0; sg < nseg; ++sg) {
           const int ks = g.nseg > 0 ? g.segK[sg] : g.K;

@@ -78,6 +78,14 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   const bool a_kc = D.sAk == 1, b_kc = D.sBk == 1;
   const TA* Ab = reinterpret_cast<const TA*>(D.A);
   const TB* Bb = reinterpret_cast<const TB*>(D.B);
+  const int msplit = D.msplit > 0 ? D.msplit : M;   // rows from here on lie a2off further
+  // element (r, k) of A in chunk segment kb
+  auto aget = [&](int kb, int r, int k) -> TM {
+    const int rr = min(r, M - 1);
+    const int64_t off = (int64_t)kb * D.sAkb + (int64_t)rr * D.sAm + (rr >= msplit ? D.a2off : 0) +
+                        (int64_t)min(k, K - 1) * D.sAk;
+    return (TM)gld(&Ab[off]) * (TM)(k < K);
+  };
 
   // loader coordinates: along k (thread t: k t % KC of rows t / KC + (256 / KC) u,
   // so that KC consecutive lanes read one row's chunk and write one LDS row)
@@ -87,13 +95,9 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   TM ra[LU], rb[LU];
   auto load = [&](int c) {
     const int kb = c / cpb, k0 = (c % cpb) * RK_KC;
-    const TA* Ak = Ab + (int64_t)kb * D.sAkb;
     if constexpr (KM) {   // thread t: row t % 128, k from (t / 128) * LU
 #pragma unroll
-      for (int u = 0; u < LU; ++u) {
-        const int r = tid & 127, k = k0 + (tid >> 7) * LU + u;
-        ra[u] = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]) * (TM)(k < K);
-      }
+      for (int u = 0; u < LU; ++u) ra[u] = aget(kb, tid & 127, k0 + (tid >> 7) * LU + u);
       const TB* Bk = Bb + (int64_t)kb * D.sBkb;
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
@@ -106,8 +110,7 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
     for (int u = 0; u < LU; ++u) {
       const int r = a_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
       const int k = a_kc ? k0 + tid % RK_KC : k0 + tid / RG;
-      const TM v = (TM)gld(&Ak[(int64_t)min(r, M - 1) * D.sAm + (int64_t)min(k, K - 1) * D.sAk]);
-      ra[u] = v * (TM)(k < K);
+      ra[u] = aget(kb, r, k);
     }
     if (!SAMEB) {
       const TB* Bk = Bb + (int64_t)kb * D.sBkb;

@@ -43,6 +43,11 @@ struct GemmDesc {
   int64_t krld1, krld2;
   double alpha;
   const double* alpha_dev;  // if set, alpha is multiplied by *alpha_dev
+  // Rows m >= msplit of A (msplit > 0) lie a2off elements further on, at
+  // A + m*sAm + a2off: the Gram matrix of two frames with the same row
+  // stride side by side, each in its own buffer.  Split-K Gram launches only.
+  int64_t a2off;
+  int32_t msplit;
 };
 
 // How a GEMM writes C.
