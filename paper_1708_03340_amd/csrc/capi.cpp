@@ -436,20 +436,21 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
 
 // Interleaves the launch plans of independent problems (the tensors of a
 // batch) into one plan whose launches each serve every problem at the same
-// step.  A step is identified by (kind, label, occurrence of that pair in its
-// plan).  The plans are consumed from their heads: at each turn the step taken
+// step.  A step is identified by (kind, label, stream, occurrence of that
+// triple in its plan).  The plans are consumed from their heads: at each turn the step taken
 // is one that no plan still holds behind its head, so the launches of one step
 // are merged whole; each plan's own order is kept, which is all its
 // correctness needs (the problems share no written memory).
 ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
   const int n = (int)plans.size();
-  // steps as integer ids: (kind, label, occurrence of the pair in the plan)
+  // steps as integer ids: (kind, label, stream, occurrence in the plan)
   std::map<std::string, int> ids;
   std::vector<std::vector<int>> key(n);
   for (int p = 0; p < n; ++p) {
     std::map<std::string, int> occ;
     for (const Op& op : plans[p].ops) {
-      const std::string base = std::to_string(op.kind) + "|" + (op.label ? op.label : "");
+      const std::string base =
+          std::to_string(op.kind) + "|" + (op.label ? op.label : "") + "|" + std::to_string(op.stream);
       const std::string k = base + "|" + std::to_string(occ[base]++);
       auto it = ids.emplace(k, (int)ids.size()).first;
       key[p].push_back(it->second);
@@ -1559,10 +1560,12 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     P.ops.back().p0 = O.st;
   };
   // projections (eq. (nodewisetruncation), eq. (transfertransformationtrunc), root rule)
-  // of the given leaves (by mode), inner nodes and, if root, the root
+  // of the given leaves (by mode), inner nodes (the mode-1 product with the
+  // node's own eigenvectors if m1, the products with the sons' if m23) and,
+  // if root, the root
   struct ProjLabels { const char *factor, *leaf, *m1, *m2, *m3, *root; };
   auto emit_proj = [&](const std::vector<int>& modes, const std::vector<int>& inner, bool root,
-                       const ProjLabels& L) {
+                       const ProjLabels& L, bool m1, bool m23) {
     std::vector<GemmDesc> dp, du, d1, d2, d3;
     for (int mu : modes) {
       const int t = tr.leaf_node[mu];
@@ -1615,12 +1618,16 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     add_gemm(P, dp, F64, F64, T, MATH_F64, GEMM_STORE, true, false);
     g_label = L.leaf;
     add_gemm(P, du, X[0].frame_dtype, T, need ? F64 : out->frame_dtype, fmath, GEMM_STORE, false, false, true);
-    g_label = L.m1;
-    add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false, true);
-    g_label = L.m2;
-    add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
-    g_label = L.m3;
-    add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true, true);
+    if (m1) {
+      g_label = L.m1;
+      add_gemm(P, d1, T, T, T, fmath, GEMM_STORE, true, false, true);
+    }
+    if (m23) {
+      g_label = L.m2;
+      add_gemm(P, d2, T, T, T, fmath, GEMM_STORE, true, false, true);
+      g_label = L.m3;
+      add_gemm(P, d3, T, T, need ? F64 : out->transfer_dtype, fmath, GEMM_STORE, true, true, true);
+    }
     if (root) {
       g_label = L.root;
       // root: Qm_t1^T BDo Qm_t2
@@ -1655,20 +1662,25 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
                            "proj_inner_mode3", "proj_root"};
   const ProjLabels lab_up{"proj_leaf_factor_upper", "proj_leaf_upper", "proj_inner_mode1_upper",
                           "proj_inner_mode2_upper", "proj_inner_mode3_upper", "proj_root_upper"};
+  // the mode-1 products of the inner nodes with lower sons need only their
+  // own (upper) eigenvectors: they follow the upper projections on the
+  // second stream, beside the lower eigensolver
   auto upper_part = [&](int dep) {
     if (!split || dep != Dmax - 2) return;
     add_sync(P, OP_FORK);
     g_stream = 1;
     emit_eig(up_nodes, "eig_upper");
     emit_rank_prep(up_nodes, "rank_select_upper", "proj_prep_upper");
-    emit_proj(modes_up, inner_up, root_up, lab_up);
+    emit_proj(modes_up, inner_up, root_up, lab_up, true, true);
+    const ProjLabels lab_side{"", "", "proj_inner_mode1_side", "", "", ""};
+    emit_proj({}, inner_low, false, lab_side, true, false);
     g_stream = 0;
   };
   plan_gramians(P, tr, S.K, O.nb, O.BDo, O.st, Qo, T, upper_part);
   emit_eig(low_nodes, "eig");
   if (split) add_sync(P, OP_JOIN);
   emit_rank_prep(low_nodes, "rank_select", "proj_prep");
-  emit_proj(modes_low, inner_low, !root_up, lab_low);
+  emit_proj(modes_low, inner_low, !root_up, lab_low, !split, true);
   {
     g_label = "finish";
     StateRec r = blank_state(O.st);
