@@ -196,8 +196,9 @@ def main():
 
     def math_type(kname):
         # math type of a GEMM kernel: third template argument of gemm_kernel<A,B,math,acc64>
-        # and gemm_rk_kernel<A,B,math,mode,kc>; gemm128_kernel and gemm_sb_kernel compute in float64
-        if kname.startswith("gemm128_kernel") or kname.startswith("gemm_sb_kernel"):
+        # and gemm_rk_kernel<A,B,math,mode,kc,km>; gemm128_kernel and the streamed kernels
+        # (gemm_sb_kernel, gemm_sb_ring_kernel) compute in float64
+        if kname.startswith("gemm128_kernel") or kname.startswith("gemm_sb"):
             return "double"
         if kname.startswith("gemm_kernel") or kname.startswith("gemm_rk_kernel"):
             return kname[kname.index("<") + 1:].rstrip(">").split(",")[2]

@@ -810,8 +810,9 @@ std::string kernel_name(const Op& op) {
       if (op.g.rk) {
         const std::string tm = op.g.math == MATH_F32 ? "float" : "double";
         const int kc = op.g.rk_sym == 1 ? 32 : 16;
+        const bool km = op.g.rk_sym == 2 && !op.g.a_kcontig && !op.g.b_kcontig;
         return std::string("gemm_rk_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," + tm + "," +
-               std::to_string(op.g.rk_sym) + "," + std::to_string(kc) + ">";
+               std::to_string(op.g.rk_sym) + "," + std::to_string(kc) + "," + (km ? "true" : "false") + ">";
       }
       if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +
