@@ -342,3 +342,32 @@ def test_huge_scale(H):
     G = to_oracle(res.out)
     G.log2_scale -= 3000
     assert O.rel_diff(G, T) <= FP64_TOL
+
+
+def test_unequal_summand_ranks(H):
+    """Two summands of leaf ranks 40 and 60 (sum 100): the leaf Gram matrix of
+    the first CholeskyQR2 sweep is one split-K descriptor whose rows from 40 on
+    lie in the second frame's buffer.  Float32 and float64 frames, both paths."""
+    import torch
+    say("case unequal summand ranks 40 + 60")
+    rng = np.random.default_rng(31)
+    d = 6
+    nn = 2 * d - 1
+    tr = O.Tree(d)
+    ra = [1] + [40 if tr.is_leaf(t) else 24 for t in range(1, nn)]
+    rc = [1] + [60 if tr.is_leaf(t) else 20 for t in range(1, nn)]
+    ns = [int(x) for x in rng.integers(300, 700, size=d)]
+    A = rand_ht(rng, d, ns, ra)
+    C = rand_ht(rng, d, ns, rc)
+    r = [1] + [30] * (nn - 1)
+    for fdt in (torch.float64, torch.float32):
+        if fdt == torch.float32:   # the oracle sees the float32 values the device holds
+            for X in (A, C):
+                X.U = [u.astype(np.float32).astype(np.float64) for u in X.U]
+                X.B = {t: (b if t == 0 else b.astype(np.float32).astype(np.float64)) for t, b in X.B.items()}
+        T, _ = O.truncate(O.add(A, C, 1.0, -0.8), mode="fixed", ranks=r)
+        for prec in (0, 1):
+            res = run_trunc(H, [A, C], [1.0, -0.8], prec, H.HT_RANK_FIXED, ranks=r, fdt=fdt)
+            err = O.rel_diff(to_oracle(res.out), T)
+            say(f"  frames {fdt} prec {prec} rel err {err:.3e}")
+            assert err <= (FP64_TOL if prec == 0 else MIXED_TOL)
