@@ -59,11 +59,14 @@ typedef enum { HT_F64 = 0, HT_F32 = 1 } ht_dtype;
 
 /* HT_PREC_FP64: every product in float64 on the FP64 matrix cores.
  * HT_PREC_MIXED: the first CholeskyQR2 sweep (the Gram matrices of the leaf
- *   frames and of M_{2,3} of every transfer tensor) on the FP32 matrix cores
- *   with float32 accumulation; the float64 second sweep removes its error.
- *   Cholesky factors, inverses, the R-factor contractions, the orthogonal
- *   factors, the Gramian pass, the eigensolves and the projections are float64
- *   (float32 there costs ~1e-6 relative error at d = 64). */
+ *   frames and of M_{2,3} of every transfer tensor) may run on the FP32 matrix
+ *   cores with float32 accumulation; the float64 second sweep removes its
+ *   error.  Where the float64 split-K Gram kernel takes the shape (orders
+ *   65..128; at the leaves, two summands whose frames share a row stride) it is
+ *   used instead, being as fast.  Cholesky factors, inverses, the R-factor
+ *   contractions, the orthogonal factors, the Gramian pass, the eigensolves and
+ *   the projections are float64 (float32 there costs ~1e-6 relative error at
+ *   d = 64). */
 typedef enum { HT_PREC_FP64 = 0, HT_PREC_MIXED = 1 } ht_precision;
 
 /* Truncation rank rule (Section 3.3 "for prescribed ranks or for prescribed
