@@ -344,18 +344,21 @@ def test_huge_scale(H):
     assert O.rel_diff(G, T) <= FP64_TOL
 
 
-def test_unequal_summand_ranks(H):
-    """Two summands of leaf ranks 40 and 60 (sum 100): the leaf Gram matrix of
-    the first CholeskyQR2 sweep is one split-K descriptor whose rows from 40 on
-    lie in the second frame's buffer.  Float32 and float64 frames, both paths."""
+@pytest.mark.parametrize("k0,k1", [(40, 60), (32, 33), (32, 32), (1, 127), (127, 1)])
+def test_unequal_summand_ranks(H, k0, k1):
+    """Two summands of leaf ranks k0 and k1.  From a sum of 65 up to 128 the
+    leaf Gram matrix of the first CholeskyQR2 sweep is one split-K descriptor
+    whose rows from k0 on lie in the second frame's buffer (32 + 32 takes the
+    blockwise path).  Float32 and float64 frames, both paths."""
     import torch
-    say("case unequal summand ranks 40 + 60")
-    rng = np.random.default_rng(31)
+    say(f"case summand leaf ranks {k0} + {k1}")
+    rng = np.random.default_rng(31 + k0)
     d = 6
     nn = 2 * d - 1
     tr = O.Tree(d)
-    ra = [1] + [40 if tr.is_leaf(t) else 24 for t in range(1, nn)]
-    rc = [1] + [60 if tr.is_leaf(t) else 20 for t in range(1, nn)]
+    # inner ranks within what the sons' ranks allow (rank 1 below rank 1)
+    ra = [1] + [k0 if tr.is_leaf(t) else min(24, k0) for t in range(1, nn)]
+    rc = [1] + [k1 if tr.is_leaf(t) else min(20, k1) for t in range(1, nn)]
     ns = [int(x) for x in rng.integers(300, 700, size=d)]
     A = rand_ht(rng, d, ns, ra)
     C = rand_ht(rng, d, ns, rc)
