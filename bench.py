@@ -109,9 +109,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the truncation of one HT sum per GPU "
-              "and has no multi-GPU path (see the sharding notes in DESIGN.md); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the truncation of one HT sum runs on one GPU and "
+              "there is no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
