@@ -225,6 +225,9 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
       op.g.sb_wn = 1;
       op.g.sb_cd = k64 ? 64 : 32;
       op.g.sb_ring = four;
+      int rows = 0;   // largest row count of the small operand
+      for (const auto& d : descs) rows = std::max(rows, op.g.sb_swap ? d.N : d.M);
+      op.g.sb_rows = rows;
       const long long per = (512 + (long long)descs.size() - 1) / (long long)descs.size();
       op.g.sb_grid = (int)std::max<long long>(1, std::min(per, items));
     }
@@ -804,8 +807,9 @@ std::string kernel_name(const Op& op) {
       }
       if (op.g.sb) {
         const int ts = op.g.sb_swap ? op.g.tB : op.g.tA, tt = op.g.sb_swap ? op.g.tA : op.g.tB;
+        const int nrb = op.g.sb_rows <= 32 ? 2 : op.g.sb_rows <= 64 ? 4 : op.g.sb_rows <= 96 ? 6 : 8;
         return std::string("gemm_sb_kernel<") + tn(ts) + "," + tn(tt) + ",1," + std::to_string(op.g.sb_cd == 64 ? 64 : 32) +
-               ">";
+               "," + std::to_string(nrb) + ">";
       }
       if (op.g.rk) {
         const std::string tm = op.g.math == MATH_F32 ? "float" : "double";
@@ -2429,7 +2433,8 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (op.g.sb) {   // the streamed kernel holds the whole reduction and the small side in LDS
           int kt = 0;
           for (int sg = 0; sg < nseg; ++sg) kt += g.nseg > 0 ? g.segK[sg] : g.K;
-          if (g.KB != 1 || kt < 1 || kt > 128 || (op.g.sb_swap ? g.N : g.M) > 128)
+          const int rows = op.g.sb_swap ? g.N : g.M;
+          if (g.KB != 1 || kt < 1 || kt > 128 || rows > 128 || (!op.g.sb_ring && rows > op.g.sb_rows))
             return fail(HT_EINVAL, "validator: streamed GEMM shape " + w);
         }
         if (g.msplit > 0) {   // two frames side by side: split-K Gram launches only

@@ -41,7 +41,9 @@ __device__ __forceinline__ double ld_as_double(const char* p) {
   return (double)gld(reinterpret_cast<const T*>(p));
 }
 
-template <typename TS, typename TT, int WN, int CD>
+// NRB: row blocks of 16 that hold rows of S (2, 4, 6 or 8); the MFMAs of
+// the blocks past them are not issued.
+template <typename TS, typename TT, int WN, int CD, int NRB>
 __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __restrict__ descs, int swap,
                                                              int tC) {
   constexpr int SB_NT = 512 / WN;     // 8 / WN waves, each 16 * WN columns of a 128-column tile
@@ -126,9 +128,9 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
   load_T(it, 0, bc);
   while (true) {
     const int next = it + gridDim.x;
-    doublex4 acc[8][WN];
+    doublex4 acc[NRB][WN];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < NRB; ++i)
 #pragma unroll
       for (int j = 0; j < WN; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
     for (int c = 0; c < nchunk; ++c) {
@@ -139,11 +141,11 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
         const int k = c * CD + 4 * kk + (lane >> 4);
-        double a[8];
+        double a[NRB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = Ss[k][16 * i + (lane & 15)];
+        for (int i = 0; i < NRB; ++i) a[i] = Ss[k][16 * i + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < NRB; ++i)
 #pragma unroll
           for (int j = 0; j < WN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bc[kk][j], acc[i][j], 0, 0, 0);
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
       for (int j = 0; j < WN; ++j) {
         const int n = tn * SB_TN + wave * 16 * WN + 16 * j + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < NRB; ++i)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int m = 16 * i + 4 * v + (lane >> 4);
@@ -321,6 +323,19 @@ __global__ __launch_bounds__(512, 1) void gemm_sb_ring_kernel(const GemmDesc* __
   }
 }
 
+template <typename TS, typename TT, int CD>
+void go_sb_rows(const GemmLaunch& g, dim3 grid, hipStream_t s) {
+  // row blocks for the largest small operand of the launch
+  if (g.sb_rows <= 32)
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, CD, 2>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+  else if (g.sb_rows <= 64)
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, CD, 4>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+  else if (g.sb_rows <= 96)
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, CD, 6>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+  else
+    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, CD, 8>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+}
+
 template <typename TS, typename TT>
 hipError_t go_sb(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.sb_grid, g.ndesc, 1);
@@ -329,9 +344,9 @@ hipError_t go_sb(const GemmLaunch& g, hipStream_t s) {
   else if (g.sb_ring)
     hipLaunchKernelGGL((gemm_sb_ring_kernel<TS, TT, float>), grid, dim3(512), 0, s, g.descs, g.sb_swap);
   else if (g.sb_cd == 64)
-    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 64>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+    go_sb_rows<TS, TT, 64>(g, grid, s);
   else
-    hipLaunchKernelGGL((gemm_sb_kernel<TS, TT, 1, 32>), grid, dim3(512), 0, s, g.descs, g.sb_swap, g.tC);
+    go_sb_rows<TS, TT, 32>(g, grid, s);
   return hipGetLastError();
 }
 

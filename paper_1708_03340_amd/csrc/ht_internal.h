@@ -70,6 +70,7 @@ struct GemmLaunch {
   int sb_wn;               //   16-column MFMA blocks per wave (2: 4 waves, else 8 waves)
   int sb_cd;               //   chunk depth along k: 64 (reduction a multiple of 64) or 32
   bool sb_ring;            //   every reduction is 97 .. 128: four-buffer ring kernel
+  int sb_rows;             //   largest row count of the small operand (other kernels: 128)
   bool rk;                 // M, N <= 128, long reduction split over workgroups
   int rk_sym;              //   1: B is A^T of the same matrix; 2: symmetric result (upper blocks only)
   int rk_split;            //   workgroups per descriptor along the reduction
