@@ -401,13 +401,23 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
     return gemm_op(v, q.tA, q.tB, q.tC, q.math, q.mode, q.a_kcontig, q.b_kcontig, proto.acc64_req,
                    proto.tblocks, proto.sym_out);
   };
-  // the kernel gemm_op would pick for the descriptor alone
-  std::vector<std::vector<GemmDesc>> cls(5);
+  // the kernel gemm_op would pick for the descriptor alone; streamed
+  // products also by ring eligibility (reduction above 96) and, below it, by
+  // the row blocks of the small operand, so that a launch of small problems
+  // does not take the row count of the largest
+  constexpr int kTiled = 1000;
+  std::map<int, std::vector<GemmDesc>> cls;
   for (const auto& d : descs) {
-    int c = 4;
+    int c = kTiled;
     if (q.math == MATH_F64 && q.mode == GEMM_STORE) {
       const int w = sb_want(d);
-      if (w >= 0) c = w;
+      if (w >= 0) {
+        int kt = 0;
+        if (d.nseg > 0) for (int sg = 0; sg < d.nseg; ++sg) kt += d.segK[sg];
+        else kt = d.K;
+        const int rows = w ? d.N : d.M;
+        c = 10 + 10 * w + (kt > 96 ? 0 : 1 + (rows + 31) / 32);
+      }
     } else if (q.math == MATH_F64 && q.mode == GEMM_ATOMIC && rk_shape(d) && d.M == d.N) {
       const bool gram = q.tA == q.tB && rk_gram(d);
       if (gram || proto.sym_out) c = gram ? 2 : 3;
@@ -415,9 +425,9 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
     cls[c].push_back(d);
   }
   constexpr long long kGridMax = 65535;
-  for (int ci = 0; ci < 5; ++ci) {
-    const auto& v = cls[ci];
-    const bool tiled = ci == 4;   // only the tiled kernels put the batch on a grid axis
+  for (const auto& kv : cls) {
+    const auto& v = kv.second;
+    const bool tiled = kv.first == kTiled;   // only the tiled kernels put the batch on a grid axis
     size_t i = 0;
     while (i < v.size()) {
       std::vector<GemmDesc> chunk;
