@@ -251,6 +251,8 @@ Op gemm_op(const std::vector<GemmDesc>& descs, int tA, int tB, int tC, int math,
     if (ok && (sym || sym_out)) {
       op.g.rk = true;
       op.g.rk_sym = sym ? 1 : 2;
+      op.g.rk_part = false;
+      for (const auto& d : descs) op.g.rk_part = op.g.rk_part || std::max(d.M, d.N) <= 112;
       op.g.rk_kc = sym ? 32 : 16;
       // split-K width: about 512 workgroups, one round at two per CU
       const long long want = (512 + (long long)descs.size() - 1) / (long long)descs.size();
@@ -826,7 +828,8 @@ std::string kernel_name(const Op& op) {
         const int kc = op.g.rk_sym == 1 ? 32 : 16;
         const bool km = op.g.rk_sym == 2 && !op.g.a_kcontig && !op.g.b_kcontig;
         return std::string("gemm_rk_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," + tm + "," +
-               std::to_string(op.g.rk_sym) + "," + std::to_string(kc) + "," + (km ? "true" : "false") + ">";
+               std::to_string(op.g.rk_sym) + "," + std::to_string(kc) + "," + (km ? "true" : "false") +
+               (op.g.rk_part ? ",true" : ",false") + ">";
       }
       if (op.g.big) return std::string("gemm128_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + ">";
       return std::string("gemm_kernel<") + tn(op.g.tA) + "," + tn(op.g.tB) + "," +

@@ -47,7 +47,10 @@ template <> struct RkTraits<float> {
 
 // MODE 0: full result; 1: Gram matrix (B = A^T, upper blocks); 2: separate B
 // but a symmetric result (upper blocks, mirrored), as for the son Gramians
-template <typename TA, typename TB, typename TM, int MODE, int RK_KC, bool KM = false>
+// PART: some result of the launch has at most 112 rows, and the block
+// columns past a result are skipped (a run-time test the full-size launches do
+// not carry).
+template <typename TA, typename TB, typename TM, int MODE, int RK_KC, bool KM = false, bool PART = false>
 __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const GemmDesc* __restrict__ descs,
                                                                         int nsplit, int tC, int mode) {
   constexpr bool SYM = MODE != 0;      // upper blocks only
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   if (c0 >= c1) return;
 
   const bool a_kc = D.sAk == 1, b_kc = D.sBk == 1;
+  const int nbk = (max(M, N) + 15) >> 4;   // 16 x 16 blocks along each side holding result rows
   const TA* Ab = reinterpret_cast<const TA*>(D.A);
   const TB* Bb = reinterpret_cast<const TB*>(D.B);
   const int msplit = D.msplit > 0 ? D.msplit : M;   // rows from here on lie a2off further
@@ -208,6 +212,7 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
               for (int j = 0; j < 8; ++j) {
                 if (i == 1 && j < 4) continue;   // block row 7-w >= 4: never left of 4
                 if (j < (i == 0 ? wave : 7 - wave)) continue;
+                if (PART && j >= nbk) continue;   // block column past the result (its row is at most j)
                 acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
               }
         }
@@ -279,8 +284,10 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
               fb1 = pb[1];
             }
             const bool first = bl < nfirst;
-            acc[bl] = Tr::mfma(first ? fa0[0] : fa1[0], fb0, acc[bl]);
-            acc[bl] = Tr::mfma(first ? fa0[1] : fa1[1], fb1, acc[bl]);
+            if (!PART || col < nbk) {   // a block column past the result (its row is at most col) is skipped
+              acc[bl] = Tr::mfma(first ? fa0[0] : fa1[0], fb0, acc[bl]);
+              acc[bl] = Tr::mfma(first ? fa0[1] : fa1[1], fb1, acc[bl]);
+            }
           }
         }
       }
@@ -355,21 +362,29 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   }
 }
 
+template <typename TA, typename TB, typename TM, bool PART>
+void go_rk_part(const GemmLaunch& g, dim3 grid, hipStream_t s) {
+  if (g.rk_sym == 1)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 1, 32, false, PART>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+  else if (!g.a_kcontig && !g.b_kcontig)
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16, true, PART>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+  else
+    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16, false, PART>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
+                       g.tC, g.mode);
+}
+
 template <typename TA, typename TB, typename TM>
 hipError_t go_rk(const GemmLaunch& g, hipStream_t s) {
   dim3 grid(g.rk_split, g.ndesc, 1);
-  if (g.rk_sym == 1)
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 1, 32>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
-                       g.mode);
-  else if (g.rk_sym == 2 && !g.a_kcontig && !g.b_kcontig)
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16, true>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split,
-                       g.tC, g.mode);
-  else if (g.rk_sym == 2)
-    hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 2, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
-                       g.mode);
-  else
+  if (g.rk_sym == 0)
     hipLaunchKernelGGL((gemm_rk_kernel<TA, TB, TM, 0, 16>), grid, dim3(RK_NT), 0, s, g.descs, g.rk_split, g.tC,
                        g.mode);
+  else if (g.rk_part)
+    go_rk_part<TA, TB, TM, true>(g, grid, s);
+  else
+    go_rk_part<TA, TB, TM, false>(g, grid, s);
   return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct GemmLaunch {
   int sb_cd;               //   chunk depth along k: 64 (reduction a multiple of 64) or 32
   bool sb_ring;            //   every reduction is 97 .. 128: four-buffer ring kernel
   int sb_rows;             //   largest row count of the small operand (other kernels: 128)
+  bool rk_part;            //   split-K: some result has at most 112 rows (skip past it)
   bool rk;                 // M, N <= 128, long reduction split over workgroups
   int rk_sym;              //   1: B is A^T of the same matrix; 2: symmetric result (upper blocks only)
   int rk_split;            //   workgroups per descriptor along the reduction
