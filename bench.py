@@ -12,7 +12,9 @@ one such sum-truncation with all inputs resident in HBM.
 Prints one JSON line (stdout).  The mixed-precision path is the headline
 value; the float64 path and the fixed-rank (r = 64) reading are timed beside
 it.  `roofline` describes the kernel with the largest share of the timed
-region (HIP events around every launch, on the library's stream);
+region (HIP events around every launch, on the stream it runs on) and
+`roofline_mfma` the matrix-core kernel with the largest share; `traffic` is
+the committed rocprofv3 counter figure while the kernel sources match it.
 `cpu_baseline` times the float64 NumPy oracle on one sum-truncation of the
 same workload on the host cores.
 """
