@@ -153,6 +153,21 @@ def test_batched_plan_in_bounds(L):
     assert nl.value < 200, nl.value
 
 
+def test_single_problem_launch_count(L):
+    """The d = 64, k = 64 + 64 truncation plans one launch per step of the
+    method: the second CholeskyQR2 step forms R = R2 R1, R^-1 and the forward
+    copy inside its Cholesky launch, and each leaf's first Gram matrix is one
+    descriptor, so the plan stays near 80 launches (it was about 100 with the
+    combine in separate launches)."""
+    d = 64
+    X = (H.HtDesc * 2)(*[desc(d, 10000, uniform(d, 64)) for _ in range(2)])
+    N = (ctypes.c_int32 * 1)(2)
+    Op = (H.HtTruncOpts * 1)(opts(d, 1, eps=1e-6))
+    nl = ctypes.c_int32(0)
+    check(L, L.ht_debug_validate_truncate_batched(1, X, N, Op, ctypes.byref(nl)))
+    assert nl.value <= 85, nl.value
+
+
 def test_batched_plan_mixed_problems_in_bounds(L):
     """Different d, n, ranks, dtypes, summand counts, rank modes and precisions in one batch."""
     import numpy as np
