@@ -61,6 +61,8 @@ CASES = [
     (128, 100000, 64, 2, 0, 64, 1),
     (2, 9, 5, 2, 0, 3, 0), (3, 7, 3, 2, 0, 2, 1), (5, 3, 4, 2, 0, 3, 0), (7, 65, 37, 2, 1, 0, 1),
     (6, 129, 1, 3, 0, 2, 0), (9, 100, 48, 1, 0, 17, 1), (33, 4096, 48, 2, 1, 0, 1), (17, 100, 8, 2, 0, 8, 0),
+    (2, 1, 1, 2, 0, 1, 0), (2, 1, 1, 1, 1, 0, 1), (4, 2, 3, 2, 1, 0, 1), (3, 64, 64, 2, 1, 0, 0),
+    (8, 127, 64, 2, 0, 1, 1), (5, 300, 42, 3, 1, 0, 1),
 ]
 
 
