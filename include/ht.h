@@ -25,7 +25,14 @@
  *            is.  Launch tables for a new combination of buffers are uploaded
  *            with one synchronous copy; repeating a call with the same
  *            buffers and shapes reuses them and makes no host synchronisation.
- * Errors.    Argument and shape errors are found on the host before anything
+ * Threads.   A context may be shared by several host threads.  Each call
+ *            holds the context's lock while it looks up or uploads its launch
+ *            tables and enqueues, so launches of two calls never interleave
+ *            and no table is freed while a call still has to enqueue from it.
+ *            Calls on different streams that share a workspace or output
+ *            buffers race on the device; the caller orders them (one stream,
+ *            or events).
+ * Errors.   Argument and shape errors are found on the host before anything
  *            is enqueued and returned as an ht_status; ht_last_error() gives
  *            a human-readable reason (per thread).  Numerical events (a
  *            rank-deficient frame met by the Cholesky step, a non-finite

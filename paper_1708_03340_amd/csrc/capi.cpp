@@ -649,7 +649,7 @@ struct ProfAgg { std::string label, kernel; long long n = 0; double ms = 0, flop
 struct ht_context {
   int device = 0;
   std::mutex mu;
-  std::mutex run_mu;                     // one plan at a time uses the second stream
+  std::mutex run_mu;                     // one plan at a time uses the second stream (taken after mu)
   hipStream_t side = nullptr;            // second stream (default priority), created on first use
   std::vector<hipEvent_t> sync_events;   // fork / join events
   // the last batched call: its argument signature, merged plan and table
@@ -683,29 +683,33 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
 ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
   build_key(P);
   void* dtable = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it) {
-      if (it->key == P.key) {
-        dtable = it->dtable;
-        ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
-        break;
-      }
+  // the lock is held through the enqueue: a concurrent call could otherwise
+  // evict and free this table before its launches are queued
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it) {
+    if (it->key == P.key) {
+      dtable = it->dtable;
+      ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
+      break;
     }
-    if (!dtable && !P.table.empty()) {
-      if (ctx->cache.size() >= kCacheMax) {
-        HT_HIP(hipDeviceSynchronize());
-        (void)hipFree(ctx->cache.back().dtable);
-        ctx->cache.pop_back();
-      }
-      HT_HIP(hipMalloc(&dtable, P.table.size()));
-      HT_HIP(hipMemcpy(dtable, P.table.data(), P.table.size(), hipMemcpyHostToDevice));
-      Plan c;
-      c.key = P.key;
-      c.dtable = dtable;
-      c.dbytes = P.table.size();
-      ctx->cache.push_front(std::move(c));
+  }
+  if (!dtable && !P.table.empty()) {
+    if (ctx->cache.size() >= kCacheMax) {
+      HT_HIP(hipDeviceSynchronize());
+      (void)hipFree(ctx->cache.back().dtable);
+      ctx->cache.pop_back();
     }
+    HT_HIP(hipMalloc(&dtable, P.table.size()));
+    const hipError_t e = hipMemcpy(dtable, P.table.data(), P.table.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dtable);
+      return fail(HT_EDEVICE, std::string("plan table upload: ") + hipGetErrorString(e));
+    }
+    Plan c;
+    c.key = P.key;
+    c.dtable = dtable;
+    c.dbytes = P.table.size();
+    ctx->cache.push_front(std::move(c));
   }
   return launch_plan(ctx, P, dtable, stream);
 }
@@ -1906,7 +1910,11 @@ ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, 
   void* table = nullptr;
   if (!M.table.empty()) {
     HT_HIP(hipMalloc(&table, M.table.size()));
-    HT_HIP(hipMemcpy(table, M.table.data(), M.table.size(), hipMemcpyHostToDevice));
+    const hipError_t e = hipMemcpy(table, M.table.data(), M.table.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(table);
+      return fail(HT_EDEVICE, std::string("batch table upload: ") + hipGetErrorString(e));
+    }
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (ctx->btable) {
@@ -2277,12 +2285,14 @@ extern "C" {
 
 ht_status ht_profile_enable(ht_context* ctx, int32_t on) {
   if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->prof = on != 0;
   return HT_OK;
 }
 
 ht_status ht_profile_read(ht_context* ctx, int32_t max_entries, ht_profile_entry* out, int32_t* n_out) {
   if (!ctx || !n_out) return fail(HT_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);   // launches append to the same lists
   for (auto& p : ctx->pending) {
     HT_HIP(hipEventSynchronize(p.b));
     float ms = 0.f;
@@ -2319,6 +2329,7 @@ ht_status ht_profile_reset(ht_context* ctx) {
   if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
   int32_t n = 0;
   ht_status s = ht_profile_read(ctx, 0, nullptr, &n);
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->agg.clear();
   return s;
 }
