@@ -53,7 +53,7 @@ def cpu_baseline(cfg):
     from threadpoolctl import threadpool_info
     import htsynth as S
     from oracle import ht_oracle as O
-    a, c = S.config_pair(3)
+    a, c = S.workload_pair("d64_n1e4_k64")
     A, C = O.from_input(a), O.from_input(c)
     t0 = time.perf_counter()
     X = O.add(A, C)
@@ -131,7 +131,7 @@ def main():
         log(f"bench: copy calibration, 3 copies of {args.copy_calibration} MiB")
         del src, dst
     log("bench: generating inputs (d=64, n=1e4, k=64, float32)")
-    a, c = S.config_pair(3)
+    a, c = S.workload_pair("d64_n1e4_k64")
     A, C = H.DeviceHT.from_input(a), H.DeviceHT.from_input(c)
     torch.cuda.synchronize()
     mixed = H.Truncator([A, C], [1.0, 1.0], mode=H.HT_RANK_TOL, eps=cfg["eps"], relative=True,

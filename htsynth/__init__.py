@@ -34,7 +34,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "HTInput", "CONFIGS", "make_tensor", "make_pair", "config_pair",
+    "HTInput", "WORKLOADS", "make_tensor", "make_pair", "workload_pair",
     "batched_meta", "entry_indices",
 ]
 
@@ -102,12 +102,13 @@ def _cfg(s, d, n, k, leaf, spectrum, dtype, **trunc):
     return dict(seed_base=s, d=d, n=n, k=k, leaf=leaf, spectrum=spectrum, dtype=dtype, trunc=trunc)
 
 
-# Configurations of the workload (sizes, value distributions, truncation).
-CONFIGS = {
-    1: _cfg(1, 4, 16, 4, "normal", None, np.float64, mode="fixed", rank=4),
-    2: _cfg(2, 16, 1000, 32, "orth", ("pow", 10.0, -1.0 / 8.0), np.float64, mode="fixed", rank=32),
-    3: _cfg(3, 64, 10000, 64, "normal", ("geo", 0.9), np.float32, mode="tol", eps=1e-6, rank=64),
-    5: _cfg(5, 128, 100000, 64, "normal", ("pow", 10.0, -1.0 / 16.0), np.float32, mode="fixed", rank=64),
+# Workloads by shape: sizes, value distributions, truncation and the seed base
+# (seeds 2s and 2s+1 for the two summands).
+WORKLOADS = {
+    "d4_n16_k4": _cfg(1, 4, 16, 4, "normal", None, np.float64, mode="fixed", rank=4),
+    "d16_n1000_k32": _cfg(2, 16, 1000, 32, "orth", ("pow", 10.0, -1.0 / 8.0), np.float64, mode="fixed", rank=32),
+    "d64_n1e4_k64": _cfg(3, 64, 10000, 64, "normal", ("geo", 0.9), np.float32, mode="tol", eps=1e-6, rank=64),
+    "d128_n1e5_k64": _cfg(5, 128, 100000, 64, "normal", ("pow", 10.0, -1.0 / 16.0), np.float32, mode="fixed", rank=64),
 }
 
 
@@ -123,21 +124,21 @@ def _spectrum(spec, k):
 
 
 def make_pair(s, d, n, k, *, leaf="normal", spectrum=None, dtype=np.float64):
-    """(A, C) for configuration id s: seeds 2s and 2s+1."""
+    """(A, C) for seed base s: seeds 2s and 2s+1."""
     g = _spectrum(spectrum, k) if isinstance(spectrum, tuple) else spectrum
     a = make_tensor(2 * s, d, n, k, leaf=leaf, spectrum=g, dtype=dtype)
     c = make_tensor(2 * s + 1, d, n, k, leaf=leaf, spectrum=g, dtype=dtype)
     return a, c
 
 
-def config_pair(cid, **override):
-    """Inputs of a named configuration; keyword overrides (e.g. n=..., d=...)
+def workload_pair(name, **override):
+    """Inputs of a named workload; keyword overrides (e.g. n=..., d=...)
     shrink it for quick tests while keeping the recipe."""
-    c = dict(CONFIGS[cid])
+    c = dict(WORKLOADS[name])
     c.update(override)
     a, b = make_pair(c["seed_base"], c["d"], c["n"], c["k"], leaf=c["leaf"],
                      spectrum=c["spectrum"], dtype=c["dtype"])
-    a.meta = b.meta = dict(config=cid, trunc=c["trunc"])
+    a.meta = b.meta = dict(workload=name, trunc=c["trunc"])
     return a, b
 
 

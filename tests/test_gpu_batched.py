@@ -153,7 +153,7 @@ def test_batched_single_matches_truncate(H):
     """A batch of one gives the result of ht_truncate on the same sum."""
     import torch
     say("case batch of one vs ht_truncate")
-    a, c = S.config_pair(2, d=8, n=500)
+    a, c = S.workload_pair("d16_n1000_k32", d=8, n=500)
     da = H.DeviceHT.from_input(a)
     dc = H.DeviceHT.from_input(c)
     nn = 2 * 8 - 1

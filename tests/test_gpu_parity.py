@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
 MIXED_TOL = 1e-6
-# The config-3 recipe (N(0,1) frames, spectra 0.9^i, tolerance 1e-6) cuts
+# The d=64, n=1e4, k=64 recipe (N(0,1) frames, spectra 0.9^i, tolerance 1e-6) cuts
 # where lambda_r / lambda_1 ~ 3e-14 with relative gaps ~2e-15: the FP64
 # Gramians cannot resolve the kept subspace there, and the oracle itself moves
 # by 1.4e-9 (d=16) / 2.1e-9 (d=64) when its inputs change by 1e-16.  The FP64
@@ -83,11 +83,11 @@ def oracle_sum(Xs, coef):
     return Y
 
 
-# ------------------------------------------------------------------ config 1 (d=4, n=16, k=4)
+# ------------------------------------------------------------------ workload d=4, n=16, k=4
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config1_fixed(H, prec):
-    say(f"case config1 fixed prec={prec}")
-    a, c = S.config_pair(1)
+def test_d4_n16_k4_fixed(H, prec):
+    say(f"case d4_n16_k4 fixed prec={prec}")
+    a, c = S.workload_pair("d4_n16_k4")
     A, C = O.from_input(a), O.from_input(c)
     X = O.add(A, C)
     T, info = O.truncate(X, mode="fixed", ranks=[4] * 7)
@@ -170,11 +170,11 @@ def test_add(H):
     np.testing.assert_allclose(O.full(G), O.full(R), rtol=1e-14, atol=1e-14 * np.abs(O.full(R)).max())
 
 
-# ------------------------------------------------------------------ config 2 (d=16, n=1000, k=32, spectrum 10^(-i/8))
+# ------------------------------------------------------------------ workload d=16, n=1000, k=32, spectrum 10^(-i/8)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config2(H, prec):
-    say(f"case config2 prec={prec}")
-    a, c = S.config_pair(2)
+def test_d16_n1000_k32(H, prec):
+    say(f"case d16_n1000_k32 prec={prec}")
+    a, c = S.workload_pair("d16_n1000_k32")
     A, C = O.from_input(a), O.from_input(c)
     X = O.add(A, C)
     nn = 2 * 16 - 1
@@ -192,11 +192,11 @@ def test_config2(H, prec):
     assert worst <= (1e-13 if prec == 0 else 1e-6)
 
 
-# ------------------------------------------------------------------ config 3 recipe at reduced d and n
-def test_config3_reduced_tolerance(H):
-    say("case config3 recipe d=8 n=2000 k=64 tol 1e-6 mixed")
+# ------------------------------------------------------------------ the d=64, n=1e4, k=64 recipe at reduced d and n
+def test_d64_recipe_reduced_tolerance(H):
+    say("case d64_n1e4_k64 recipe at d=8 n=2000 k=64 tol 1e-6 mixed")
     import torch
-    a, c = S.config_pair(3, d=8, n=2000)
+    a, c = S.workload_pair("d64_n1e4_k64", d=8, n=2000)
     A, C = O.from_input(a), O.from_input(c)
     X = O.add(A, C)
     T, info = O.truncate(X, mode="tol", eps=1e-6, relative=True)
@@ -217,12 +217,12 @@ def test_config3_reduced_tolerance(H):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config3_full_size(H, prec):
+def test_d64_n1e4_k64_full_size(H, prec):
     """The benchmark's workload at full size: GPU vs oracle on the whole
     truncated tensor (tolerance mode; parity at the oracle's ranks)."""
-    say(f"case config3 full size prec={prec}")
+    say(f"case d64_n1e4_k64 full size prec={prec}")
     import torch
-    a, c = S.config_pair(3)
+    a, c = S.workload_pair("d64_n1e4_k64")
     A, C = O.from_input(a), O.from_input(c)
     X = O.add(A, C)
     T, info = O.truncate(X, mode="tol", eps=1e-6, relative=True)
@@ -293,7 +293,7 @@ def test_n_smaller_than_rank(H):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_a_plus_a_is_2a(H, prec):
     say(f"case A+A prec={prec}")
-    a, _ = S.config_pair(2, d=8)
+    a, _ = S.workload_pair("d16_n1000_k32", d=8)
     A = O.from_input(a)
     res = run_trunc(H, [A, A], [1.0, 1.0], prec, H.HT_RANK_FIXED, ranks=[32] * 15)
     err = O.rel_diff(to_oracle(res.out), O.add(A, A, 2.0, 0.0))
@@ -306,7 +306,7 @@ def test_a_plus_a_is_2a(H, prec):
 
 def test_zero_partner_and_three_summands(H):
     say("case zero partner, three summands")
-    a, c = S.config_pair(1)
+    a, c = S.workload_pair("d4_n16_k4")
     A, C = O.from_input(a), O.from_input(c)
     res = run_trunc(H, [A, C], [1.0, 0.0], 0, H.HT_RANK_FIXED, ranks=[4] * 7)
     assert O.rel_diff(to_oracle(res.out), A) <= FP64_TOL
@@ -320,7 +320,7 @@ def test_zero_partner_and_three_summands(H):
 
 def test_tolerance_extremes(H):
     say("case eps >= 1 and eps = 0")
-    a, c = S.config_pair(1)
+    a, c = S.workload_pair("d4_n16_k4")
     A, C = O.from_input(a), O.from_input(c)
     res = run_trunc(H, [A, C], [1.0, 1.0], 0, H.HT_RANK_TOL, eps=2.0)
     assert res.ranks[1:] == [1] * 6
@@ -333,7 +333,7 @@ def test_tolerance_extremes(H):
 def test_huge_scale(H):
     """Scale exponents far outside float64: the result's scale shifts exactly."""
     say("case huge scale")
-    a, c = S.config_pair(1)
+    a, c = S.workload_pair("d4_n16_k4")
     A, C = O.from_input(a), O.from_input(c)
     A.log2_scale = C.log2_scale = 3000
     res = run_trunc(H, [A, C], [1.0, 1.0], 0, H.HT_RANK_FIXED, ranks=[4] * 7)

@@ -219,7 +219,7 @@ def test_projection_order_matters():
 
 
 def test_a_plus_a_is_2a():
-    a, _ = S.config_pair(1)
+    a, _ = S.workload_pair("d4_n16_k4")
     A = O.from_input(a)
     T, info = O.truncate(O.add(A, A), mode="fixed", ranks=[4] * 7)
     assert O.rel_diff(T, O.add(A, A, 2.0, 0.0)) < 1e-13
@@ -227,7 +227,7 @@ def test_a_plus_a_is_2a():
 
 
 def test_zero_partner_and_full_rank_identity():
-    a, c = S.config_pair(1)
+    a, c = S.workload_pair("d4_n16_k4")
     A, C = O.from_input(a), O.from_input(c)
     T, _ = O.truncate(O.add(A, C, 1.0, 0.0), mode="fixed", ranks=[4] * 7)
     assert O.rel_diff(T, A) < 1e-13
