@@ -1,0 +1,112 @@
+"""Checks on the compiled gfx950 code that no CPU run of the kernels can show.
+
+A chunk loop that prefetches the next chunk into registers only hides the
+load latency if those loads are still in flight when the current chunk's
+MFMAs issue.  The compiler waits for a load (`s_waitcnt vmcnt(N)`: all but the
+N most recent vector-memory operations done) before the first instruction that
+reads its result or overwrites its register.  These tests compile the GEMM
+sources to device assembly with the library's own flags and, for every global
+load that reaches an MFMA with no barrier in between, check whether the load
+is waited for before that MFMA."""
+import os
+import re
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from paper_1708_03340_amd import build as B
+
+pytestmark = pytest.mark.skipif(not os.path.exists(B.HIPCC), reason="hipcc not found")
+
+_VMEM = re.compile(r"^\s*(global_|buffer_|flat_)(load|store|atomic)")
+_WAIT = re.compile(r"vmcnt\((\d+)\)")
+
+
+def _asm(tmp, src):
+    out = os.path.join(tmp, src + ".s")
+    flags = [f for f in B.COMMON if f != "-fPIC"]
+    r = subprocess.run([B.HIPCC, *flags, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o", out],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    with open(out) as f:
+        return f.read().split("\n")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    tmp = str(tmp_path_factory.mktemp("asm"))
+    srcs = ["gemm_sb.hip", "gemm_rk.hip"]
+    with ThreadPoolExecutor(len(srcs)) as ex:
+        return dict(zip(srcs, ex.map(lambda s: _asm(tmp, s), srcs)))
+
+
+def _kernels(lines, kernel):
+    """{mangled name: body lines} for every instance of `kernel`."""
+    out = {}
+    head = re.compile(r"^(_Z\w*" + kernel + r"I\w*):")
+    for i, l in enumerate(lines):
+        m = head.match(l)
+        if m and m.group(1) not in out:
+            j = i + 1
+            while j < len(lines) and not lines[j].startswith(".Lfunc_end"):
+                j += 1
+            out[m.group(1)] = lines[i:j]
+    return out
+
+
+def prefetch_waits(body):
+    """(loads that reach an MFMA with no barrier between, those among them
+    waited for before that MFMA)."""
+    total = waited = 0
+    for j, x in enumerate(body):
+        if not re.match(r"^\s*global_load", x):
+            continue
+        after, k, w = 0, j + 1, False
+        while k < len(body) and "v_mfma" not in body[k] and "s_barrier" not in body[k]:
+            if _VMEM.match(body[k]):
+                after += 1
+            m = _WAIT.search(body[k])
+            if m and after >= int(m.group(1)):
+                w = True
+            k += 1
+        if k < len(body) and "v_mfma" in body[k]:
+            total += 1
+            waited += w
+    return total, waited
+
+
+def test_checker_sees_a_wait():
+    # a load whose value the next instruction needs, then an MFMA
+    body = ["\tglobal_load_dwordx2 v[0:1], v[2:3], off", "\ts_waitcnt vmcnt(0)",
+            "\tv_mfma_f64_16x16x4_f64 v[4:11], v[0:1], v[0:1], v[4:11]"]
+    assert prefetch_waits(body) == (1, 1)
+    # two loads, only the older one waited for
+    body = ["\tglobal_load_dwordx2 v[0:1], v[2:3], off", "\tglobal_load_dwordx2 v[12:13], v[2:3], off",
+            "\ts_waitcnt vmcnt(1)", "\tv_mfma_f64_16x16x4_f64 v[4:11], v[0:1], v[0:1], v[4:11]"]
+    assert prefetch_waits(body) == (2, 1)
+    # a barrier in between: not a prefetch of the MFMA's chunk loop
+    body = ["\tglobal_load_dwordx2 v[0:1], v[2:3], off", "\ts_barrier",
+            "\tv_mfma_f64_16x16x4_f64 v[4:11], v[0:1], v[0:1], v[4:11]"]
+    assert prefetch_waits(body) == (0, 0)
+
+
+def test_ring_kernels_keep_prefetch_in_flight(asm):
+    ks = _kernels(asm["gemm_sb.hip"], "gemm_sb_ring_kernel")
+    assert ks
+    for name, body in ks.items():
+        total, waited = prefetch_waits(body)
+        assert total > 0, name
+        assert waited == 0, f"{name}: {waited} of {total} prefetch loads waited for before an MFMA"
+
+
+@pytest.mark.xfail(strict=True, reason="the split-K loader masks and converts each value as it is loaded, "
+                                       "so the next chunk's loads are waited for before the products")
+def test_split_k_float64_prefetch_in_flight(asm):
+    ks = _kernels(asm["gemm_rk.hip"], "gemm_rk_kernel")
+    f64 = {n: b for n, b in ks.items() if "kernelIddd" in n}
+    assert f64
+    for name, body in f64.items():
+        total, waited = prefetch_waits(body)
+        assert total > 0, name
+        assert waited == 0, f"{name}: {waited} of {total} prefetch loads waited for before an MFMA"
