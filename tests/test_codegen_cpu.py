@@ -146,3 +146,15 @@ def test_gram_products_unbranched(asm):
     for name, body in _split_k(asm, 1, False).items():
         nm, nb = branches_between_products(body)
         assert nm > 0 and nb == 0, f"{name}: {nb} branches between {nm} MFMAs"
+
+
+def test_streamed_and_general_products_unbranched(asm):
+    sel = {}
+    sel.update(_kernels(asm["gemm_sb.hip"], "gemm_sb_ring_kernel"))
+    sel.update(_kernels(asm["gemm_sb.hip"], "gemm_sb_kernel"))
+    sel.update({n: b for n, b in _kernels(asm["gemm_rk.hip"], "gemm_rk_kernel").items()
+                if re.search(r"kernelI[fd]{3}Li0E", n)})    # general mode: full 128 x 128 result
+    assert len(sel) > 20
+    for name, body in sel.items():
+        nm, nb = branches_between_products(body)
+        assert nm > 0 and nb == 0, f"{name}: {nb} branches between {nm} MFMAs"
