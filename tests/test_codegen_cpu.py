@@ -9,7 +9,8 @@ sources to device assembly with the library's own flags and, for every global
 load that reaches an MFMA with no barrier in between, check whether the load
 is waited for before that MFMA.  They also count the exec-mask saves and
 branches between consecutive MFMAs: a product behind a branch costs a wait for
-every outstanding LDS read."""
+every outstanding LDS read.  Every kernel of every source is also checked for
+register spills, scratch memory and its static LDS size."""
 import os
 import re
 import subprocess
@@ -38,7 +39,7 @@ def _asm(tmp, src):
 @pytest.fixture(scope="module")
 def asm(tmp_path_factory):
     tmp = str(tmp_path_factory.mktemp("asm"))
-    srcs = ["gemm_sb.hip", "gemm_rk.hip"]
+    srcs = [f for f in B.SOURCES if f.endswith(".hip")]
     with ThreadPoolExecutor(len(srcs)) as ex:
         return dict(zip(srcs, ex.map(lambda s: _asm(tmp, s), srcs)))
 
@@ -158,3 +159,39 @@ def test_streamed_and_general_products_unbranched(asm):
     for name, body in sel.items():
         nm, nb = branches_between_products(body)
         assert nm > 0 and nb == 0, f"{name}: {nb} branches between {nm} MFMAs"
+
+
+LDS_BYTES = 160 * 1024   # per workgroup on gfx950
+
+
+def _metadata(lines):
+    """{kernel name: {key: int}} from the code object metadata in the assembly."""
+    out = {}
+    for blk in "\n".join(lines).split("\n  - ")[1:]:
+        m = re.search(r"\.name:\s+(\S+)", blk)
+        if not m or ".vgpr_count" not in blk:
+            continue
+        out[m.group(1)] = {k: int(v) for k, v in re.findall(r"\.(\w+):\s+(\d+)\s*$", blk, re.M)}
+    return out
+
+
+def test_no_spills_scratch_or_lds_overflow(asm):
+    n = 0
+    for src, lines in asm.items():
+        for name, md in _metadata(lines).items():
+            n += 1
+            assert md.get("vgpr_spill_count", 0) == 0, f"{src} {name}: VGPR spills"
+            assert md.get("private_segment_fixed_size", 0) == 0, f"{src} {name}: scratch memory"
+            assert md.get("group_segment_fixed_size", 0) <= LDS_BYTES, f"{src} {name}: LDS"
+    assert n > 100
+
+
+def test_metadata_parser_reads_the_fields():
+    lines = ["amdhsa.kernels:", "  - .agpr_count:     0", "    .group_segment_fixed_size: 150056",
+             "    .name:           k1", "    .private_segment_fixed_size: 16", "    .vgpr_count:     352",
+             "    .vgpr_spill_count: 3", "  - .group_segment_fixed_size: 0", "    .name:           k2",
+             "    .vgpr_count:     12"]
+    md = _metadata(lines)
+    assert md["k1"]["group_segment_fixed_size"] == 150056
+    assert md["k1"]["vgpr_spill_count"] == 3 and md["k1"]["private_segment_fixed_size"] == 16
+    assert md["k2"]["vgpr_count"] == 12 and "vgpr_spill_count" not in md["k2"]
