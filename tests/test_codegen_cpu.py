@@ -195,3 +195,16 @@ def test_metadata_parser_reads_the_fields():
     assert md["k1"]["group_segment_fixed_size"] == 150056
     assert md["k1"]["vgpr_spill_count"] == 3 and md["k1"]["private_segment_fixed_size"] == 16
     assert md["k2"]["vgpr_count"] == 12 and "vgpr_spill_count" not in md["k2"]
+
+
+def test_split_k_gram_modes_fit_two_workgroups_per_cu(asm):
+    # The split-K launches size their reduction split for two 4-wave
+    # workgroups on each CU: 2 waves per SIMD, so at most 256 of the 512
+    # unified (arch + accumulation) registers per wave, and half the LDS.
+    md = _metadata(asm["gemm_rk.hip"])
+    sel = {n: v for n, v in md.items() if re.search(r"kernelI[fd]{3}Li[12]E", n)}
+    assert len(sel) >= 32
+    for name, v in sel.items():
+        assert v["max_flat_workgroup_size"] == 256, name
+        assert v["vgpr_count"] <= 256, f"{name}: {v['vgpr_count']} registers"
+        assert v["group_segment_fixed_size"] <= LDS_BYTES // 2, name
