@@ -208,3 +208,14 @@ def test_split_k_gram_modes_fit_two_workgroups_per_cu(asm):
         assert v["max_flat_workgroup_size"] == 256, name
         assert v["vgpr_count"] <= 256, f"{name}: {v['vgpr_count']} registers"
         assert v["group_segment_fixed_size"] <= LDS_BYTES // 2, name
+
+
+def test_small_eigensolvers_fit_two_nodes_per_cu(asm):
+    # orders <= 64 and <= 96 (the batched workload) run two nodes per CU
+    md = _metadata(asm["eig.hip"])
+    sel = {n: v for n, v in md.items() if re.search(r"eig_kernelILi(64|96)E", n)}
+    assert len(sel) == 2
+    for name, v in sel.items():
+        waves = v["max_flat_workgroup_size"] // 64
+        assert 2 * waves <= 8 and v["vgpr_count"] <= 256, name   # 2 waves per SIMD
+        assert 2 * v["group_segment_fixed_size"] <= LDS_BYTES, name
