@@ -47,22 +47,40 @@ def timed(fn, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(cfg):
-    """One sum-truncation of the same workload by the float64 oracle."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, reps=3):
+    """Sum-truncations of the same workload by the float64 oracle: the median
+    wall clock of `reps` runs (input generation excluded)."""
+    import statistics
     from threadpoolctl import threadpool_info
     import htsynth as S
     from oracle import ht_oracle as O
     a, c = S.workload_pair("d64_n1e4_k64")
     A, C = O.from_input(a), O.from_input(c)
-    t0 = time.perf_counter()
-    X = O.add(A, C)
-    O.truncate(X, mode="tol", eps=cfg["eps"], relative=True)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        X = O.add(A, C)
+        O.truncate(X, mode="tol", eps=cfg["eps"], relative=True)
+        times.append(time.perf_counter() - t0)
+        log(f"bench: oracle sum-truncation {times[-1]:.2f} s")
+    dt = statistics.median(times)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return dict(value=1.0 / dt, unit="sum-truncations/s", cores=int(threads), kind="oracle",
-                sample=f"one full sum-truncation of the same workload (d=64, n=1e4, k=64+64, rel. tol "
-                       f"{cfg['eps']:g}) by the float64 NumPy oracle, {dt:.1f} s wall clock")
+                nproc=os.cpu_count(), cpu_model=cpu_model(), runs_s=[round(t, 3) for t in times],
+                sample=f"median of {reps} full sum-truncations of the same workload (d=64, n=1e4, k=64+64, "
+                       f"rel. tol {cfg['eps']:g}) by the float64 NumPy oracle, {dt:.1f} s each; "
+                       f"cores = BLAS threads used")
 
 
 def kernel_source_digest():

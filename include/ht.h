@@ -89,8 +89,11 @@ typedef enum { HT_RANK_FIXED = 0, HT_RANK_TOL = 1 } ht_rank_mode;
 #define HT_FLAG_RANK_DEFICIENT 1u   /* a Cholesky pivot vanished: that direction was dropped */
 #define HT_FLAG_NONFINITE      2u   /* a NaN or Inf was met */
 #define HT_FLAG_CAPPED         4u   /* max_rank stopped a node before eps was met */
-/* bits 8-15 of the flags word: the largest number of QL iterations per
- * eigenvalue (rounded down) any node's eigensolve needed (diagnostic) */
+#define HT_FLAG_NOCONV         8u   /* an eigenvalue of a Gramian was not resolved to working
+                                       precision by the eigensolver's iteration limit; its
+                                       eigenpair is used as it stands */
+/* bits 8-15 of the flags word: the largest number of iterations any single
+ * eigenvalue of any node's eigensolve needed (diagnostic, capped at 255) */
 
 typedef struct ht_context ht_context;
 

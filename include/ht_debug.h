@@ -20,6 +20,12 @@ ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_tr
 /* also returns the number of launches of the merged plan (n_launches may be NULL) */
 ht_status ht_debug_validate_truncate_batched(int32_t count, const ht_desc* X, const int32_t* n_in,
                                              const ht_trunc_opts* opts, int32_t* n_launches);
+/* Builds the launch plan of ht_truncate twice for the same arguments (fake
+ * addresses) and reports whether the two plan-cache keys are byte-identical
+ * (*equal = 1), as they must be for a repeated call to reuse its uploaded
+ * launch tables; *hash (may be NULL) is a 64-bit FNV-1a hash of the key. */
+ht_status ht_debug_plan_key_repeats(const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts, int32_t* equal,
+                                    uint64_t* hash);
 ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision);
 ht_status ht_debug_validate_gramians(const ht_desc* X);
 ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m);

@@ -223,8 +223,11 @@ def entries(X: HT, idx: np.ndarray) -> np.ndarray:
         else:
             s1, s2 = tr.sons[t]
             B = _as3(X, t)
-            # (U_t)_{i_t, q} = sum_{j,l} (B_t)_{q,j,l} (U_s1)_{i_s1, j} (U_s2)_{i_s2, l}
-            y = np.einsum("qjl,mj,ml->mq", B, rows[s1], rows[s2])
+            # (U_t)_{i_t, q} = sum_{j,l} (B_t)_{q,j,l} (U_s1)_{i_s1, j} (U_s2)_{i_s2, l},
+            # the double sum taken as the sum over j (one matrix product) and
+            # then the sum over l
+            inner_j = np.tensordot(rows[s1], B, axes=([1], [1]))     # [m, q, l]
+            y = np.einsum("mql,ml->mq", inner_j, rows[s2])
             e = expo[s1] + expo[s2]
         mx = np.max(np.abs(y), axis=1)
         ee = np.array([_exp2(v) for v in mx], dtype=np.int64)

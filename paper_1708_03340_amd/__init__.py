@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libht.so")
 HT_F64, HT_F32 = 0, 1
 HT_PREC_FP64, HT_PREC_MIXED = 0, 1
 HT_RANK_FIXED, HT_RANK_TOL = 0, 1
-HT_FLAG_RANK_DEFICIENT, HT_FLAG_NONFINITE, HT_FLAG_CAPPED = 1, 2, 4
+HT_FLAG_RANK_DEFICIENT, HT_FLAG_NONFINITE, HT_FLAG_CAPPED, HT_FLAG_NOCONV = 1, 2, 4, 8
 KMAX = 128
 
 EXPORTS = [

@@ -632,13 +632,39 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
   return HT_OK;
 }
 
+// The cache key of a plan: every field of every launch, appended one by one
+// (the structs themselves hold padding whose bytes are not defined), then
+// the argument table (its records are cleared before they are filled, so
+// their padding is zero).
+template <typename T>
+static void key_put(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+  k.insert(k.end(), b, b + sizeof(T));
+}
+
 void build_key(Plan& P) {
-  P.key.clear();
-  for (auto& op : P.ops) {
-    const unsigned char* b = reinterpret_cast<const unsigned char*>(&op);
-    P.key.insert(P.key.end(), b, b + sizeof(Op));
+  std::vector<unsigned char>& k = P.key;
+  k.clear();
+  k.reserve(P.ops.size() * 256 + P.table.size());
+  for (const Op& op : P.ops) {
+    key_put(k, op.kind);
+    const GemmLaunch& g = op.g;
+    const int gi[] = {g.tA, g.tB, g.tC, g.math, g.mode, (int)g.a_kcontig, (int)g.b_kcontig, g.splitk,
+                      (int)g.acc64, (int)g.big, (int)g.sb, (int)g.sb_swap, g.sb_grid, g.sb_wn, g.sb_cd,
+                      (int)g.sb_ring, g.sb_rows, (int)g.rk_part, (int)g.rk, g.rk_sym, g.rk_split, g.rk_kc,
+                      g.ndesc, g.maxbatch, g.maxtiles};
+    for (int x : gi) key_put(k, x);
+    key_put(k, op.toff); key_put(k, op.count); key_put(k, op.toff2); key_put(k, op.count2);
+    key_put(k, op.p0); key_put(k, op.p1); key_put(k, op.p2);
+    key_put(k, op.bytes); key_put(k, op.scale0);
+    const int oi[] = {op.i0, op.i1, op.i2, op.i3, op.i4, op.i5, op.tblocks, (int)op.sym_out,
+                      (int)op.acc64_req, op.stream};
+    for (int x : oi) key_put(k, x);
+    key_put(k, op.f0);
+    for (int64_t c : op.c) key_put(k, c);
+    key_put(k, op.label);
   }
-  P.key.insert(P.key.end(), P.table.begin(), P.table.end());
+  k.insert(k.end(), P.table.begin(), P.table.end());
 }
 
 }  // namespace
@@ -1718,8 +1744,10 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
 ht_status ht_truncate_workspace(ht_context* ctx, const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts,
                                 size_t* bytes) {
   if (!bytes) return fail(HT_EINVAL, "bytes is NULL");
+  if (!X) return fail(HT_EINVAL, "X is NULL");
+  if (n_in < 1 || n_in > MAX_SEG) return fail(HT_EINVAL, "n_in must be in [1, 8]");
   Plan P;
-  for (int c = 0; c < n_in && X; ++c) {
+  for (int c = 0; c < n_in; ++c) {
     ht_status s = check_desc(&X[c], "X[c]", false);
     if (s) return s;
   }
@@ -2648,6 +2676,53 @@ ht_status ht_debug_validate_truncate(const ht_desc* X, int32_t n_in, const ht_tr
                       (uint32_t*)flags, (double*)sigma, ws, P, nullptr);
   if (st) return st;
   return validate_plan(P, 0);
+}
+
+ht_status ht_debug_plan_key_repeats(const ht_desc* X, int32_t n_in, const ht_trunc_opts* opts, int32_t* equal,
+                                    uint64_t* hash) {
+  if (!X || !opts || !equal || n_in < 1 || n_in > MAX_SEG) return fail(HT_EINVAL, "bad argument");
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_truncate_workspace(nullptr, X, n_in, opts, &need);
+  if (st) return st;
+  FakeSpace F;
+  std::vector<FakeTensor> fx(n_in);
+  std::vector<ht_desc> xs(n_in);
+  Tree tr(X[0].d);
+  for (int c = 0; c < n_in; ++c) {
+    std::vector<int> rk(X[c].rank, X[c].rank + tr.nn);
+    fake_tensor(F, &X[c], rk, X[c].frame_dtype, X[c].transfer_dtype, fx[c], "X");
+    xs[c] = fx[c].desc;
+  }
+  SumInfo S;
+  if ((st = sum_info(xs.data(), nullptr, n_in, S))) return st;
+  std::vector<int> rc(tr.nn, 1);
+  for (int t = 1; t < tr.nn; ++t)
+    rc[t] = opts->mode == HT_RANK_FIXED ? std::min(opts->ranks[t], S.K[t])
+                                        : (opts->max_rank > 0 ? std::min(opts->max_rank, S.K[t]) : S.K[t]);
+  if (opts->mode == HT_RANK_TOL) rc[tr.son1[0]] = rc[tr.son2[0]] = std::min(rc[tr.son1[0]], rc[tr.son2[0]]);
+  FakeTensor fo;
+  const int T = opts->precision == HT_PREC_MIXED ? HT_F32 : HT_F64;
+  fake_tensor(F, &X[0], rc, T, T, fo, "out");
+  void* scale = F.get(8, "out_scale");
+  void* ws = F.get(need, "ws-total");
+  std::vector<double> coef(n_in, 1.0);
+  std::vector<unsigned char> keys[2];
+  for (int rep = 0; rep < 2; ++rep) {
+    Plan P;
+    st = build_truncate(nullptr, xs.data(), coef.data(), n_in, opts, &fo.desc, nullptr, (int64_t*)scale, nullptr,
+                        nullptr, ws, P, nullptr);
+    if (st) return st;
+    build_key(P);
+    keys[rep].swap(P.key);
+  }
+  *equal = keys[0] == keys[1] ? 1 : 0;
+  if (hash) {   // FNV-1a of the first key
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char b : keys[0]) h = (h ^ b) * 1099511628211ull;
+    *hash = h;
+  }
+  return HT_OK;
 }
 
 ht_status ht_debug_validate_truncate_batched(int32_t count, const ht_desc* X, const int32_t* n_in,

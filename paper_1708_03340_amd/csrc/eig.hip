@@ -63,7 +63,6 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
   __shared__ int sw_state[2], sw_m[2], sw_lo[2];
   __shared__ double part[16];
   __shared__ int rankpos[KT];
-  __shared__ int sh_iters;
   const SmallArgs& a = args[blockIdx.x];
   if (a.st) st = a.st;
   const int K = a.K, ld = K + 1;
@@ -169,7 +168,6 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       }
     if (tid == 0) {
       eo[K - 1] = 0.0;
-      sh_iters = 0;
       sw_state[0] = sw_state[1] = SWEEP_NONE;
     }
   }
@@ -200,6 +198,8 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
   for (int off = 32; off > 0; off >>= 1) tloc = fmax(tloc, __shfl_xor(tloc, off, 64));
   const double abs_tol = 1e-18 * tloc;   // used by wave 0 only
   int l = 0, iter = 0;                   // producer state (wave 0)
+  int max_it = 0;                        // most sweeps any one eigenvalue took (wave 0)
+  bool noconv = false;                   // an eigenvalue was given up on (wave 0)
   // Finds the next sweep and writes its rotations into buffer b (wave 0 only).
   auto produce = [&](int b) {
     while (true) {
@@ -222,6 +222,8 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
         }
       }
       if (m == l || iter >= 80) {   // converged (or given up on): next eigenvalue
+        max_it = max(max_it, iter);
+        if (m != l) noconv = true;   // 80 sweeps without e[l] reaching the deflation test
         ++l;
         iter = 0;
         continue;
@@ -331,7 +333,6 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
         sw_m[b] = m;
         sw_lo[b] = lo;   // rotations m-1 .. lo were formed
         sw_state[b] = SWEEP_ROT;
-        sh_iters += 1;
       }
       return;
     }
@@ -432,7 +433,10 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
     gst(&a.lam[pos], fmax(li, 0.0));
     if (!isfinite(li)) atomicOr(&st->flags, 2u);
   }
-  if (tid == 0) atomicMax(&st->pad, min(sh_iters / K, 255));
+  if (tid == 0) {   // wave 0, lane 0: the producer's counters
+    atomicMax(&st->pad, min(max_it, 255));
+    if (noconv) atomicOr(&st->flags, 8u);
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < RB; ++i)

@@ -113,3 +113,36 @@ def test_bad_arguments_rejected(L):
     assert L.ht_truncate(None, ctypes.byref(x), None, 1, ctypes.byref(o), None, None, None, None, None,
                          None, 0, None) == 1
     assert L.ht_tree(1, None, None, None, None, None, None, None) == 1
+
+
+def test_null_and_negative_summand_counts_rejected(L):
+    """X == NULL with n_in > 0, and n_in < 0, are argument errors (no
+    dereference, no exception across the C boundary)."""
+    nb = ctypes.c_size_t(0)
+    o = _opts(H.HT_RANK_FIXED, 4, r=2)
+    assert L.ht_truncate_workspace(None, None, 2, ctypes.byref(o), ctypes.byref(nb)) == 1
+    assert b"X is NULL" in L.ht_last_error()
+    x = _host_desc(4, 16, 4)
+    assert L.ht_truncate_workspace(None, ctypes.byref(x), -3, ctypes.byref(o), ctypes.byref(nb)) == 1
+    assert L.ht_truncate_workspace(None, ctypes.byref(x), 9, ctypes.byref(o), ctypes.byref(nb)) == 1
+
+
+@pytest.mark.parametrize("d,n,k,mode,prec", [(4, 16, 4, 0, 0), (13, 300, 20, 1, 1), (64, 10000, 64, 1, 1),
+                                             (64, 10000, 64, 0, 0)])
+def test_plan_cache_key_repeats(L, d, n, k, mode, prec):
+    """Two builds of the same ht_truncate call give byte-identical plan-cache
+    keys, so a repeated call reuses its launch tables (no upload, no host
+    synchronisation); a different call gives a different key."""
+    L.ht_debug_plan_key_repeats.argtypes = [ctypes.POINTER(H.HtDesc), ctypes.c_int32,
+                                            ctypes.POINTER(H.HtTruncOpts), ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_uint64)]
+    L.ht_debug_plan_key_repeats.restype = ctypes.c_int
+    X = (H.HtDesc * 2)(_host_desc(d, n, k), _host_desc(d, n, k))
+    o = _opts(mode, d, r=k, eps=1e-6, prec=prec)
+    eq, h1 = ctypes.c_int32(0), ctypes.c_uint64(0)
+    assert L.ht_debug_plan_key_repeats(X, 2, ctypes.byref(o), ctypes.byref(eq), ctypes.byref(h1)) == 0
+    assert eq.value == 1
+    o2 = _opts(mode, d, r=max(1, k - 1), eps=1e-5, prec=prec)
+    h2 = ctypes.c_uint64(0)
+    assert L.ht_debug_plan_key_repeats(X, 2, ctypes.byref(o2), ctypes.byref(eq), ctypes.byref(h2)) == 0
+    assert eq.value == 1 and h2.value != h1.value

@@ -69,8 +69,8 @@ def test_batched_workload_256(H):
     for b, (m, r) in enumerate(zip(meta, res)):
         assert r.ranks[1:] == [m["k"]] * (2 * m["d"] - 2), b
         assert not (r.flags & H.HT_FLAG_NONFINITE), b
-    # the oracle on a sample spread over the batch (all d, n, k ranges)
-    sample = [0, 1, 2, 3, 37, 64, 101, 128, 170, 200, 233, 255]
+    # the oracle on every 8th problem (32 of 256, all d, n, k ranges) and the last one
+    sample = list(range(0, 256, 8)) + [255]
     worst = 0.0
     for b in sample:
         m = meta[b]

@@ -21,7 +21,9 @@ MIXED_TOL = 1e-6
 # where lambda_r / lambda_1 ~ 3e-14 with relative gaps ~2e-15: the FP64
 # Gramians cannot resolve the kept subspace there, and the oracle itself moves
 # by 1.4e-9 (d=16) / 2.1e-9 (d=64) when its inputs change by 1e-16.  The FP64
-# gate for that recipe is five times the oracle's own spread.
+# gate for that recipe is five times the oracle's own spread
+# (tests/test_oracle_noise.py measures it on the CPU; the same workload at
+# fixed rank 64 is held to FP64_TOL).
 FP64_TOL_CUT_AT_NOISE = 1e-8
 
 
@@ -216,16 +218,24 @@ def test_d64_recipe_reduced_tolerance(H):
     assert O.rel_diff(G, X) <= 1e-6 * (1 + 1e-6) + 2e-7
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_d64_n1e4_k64_full_size(H, prec):
-    """The benchmark's workload at full size: GPU vs oracle on the whole
-    truncated tensor (tolerance mode; parity at the oracle's ranks)."""
-    say(f"case d64_n1e4_k64 full size prec={prec}")
-    import torch
+@pytest.fixture(scope="module")
+def d64():
+    """The d=64, n=1e4, k=64 workload, its oracle sum and the oracle's
+    tolerance-mode truncation (computed once for the full-size cases)."""
     a, c = S.workload_pair("d64_n1e4_k64")
     A, C = O.from_input(a), O.from_input(c)
     X = O.add(A, C)
     T, info = O.truncate(X, mode="tol", eps=1e-6, relative=True)
+    return dict(a=a, c=c, A=A, C=C, X=X, T=T, info=info)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_d64_n1e4_k64_full_size(H, prec, d64):
+    """The benchmark's workload at full size: GPU vs oracle on the whole
+    truncated tensor (tolerance mode; parity at the oracle's ranks)."""
+    say(f"case d64_n1e4_k64 full size prec={prec}")
+    import torch
+    a, c, T, info = d64["a"], d64["c"], d64["T"], d64["info"]
     devs = [H.DeviceHT.from_input(a), H.DeviceHT.from_input(c)]
     tr = H.Truncator(devs, [1.0, 1.0], mode=H.HT_RANK_TOL, eps=1e-6, relative=True, precision=prec,
                      out_frame_dtype=torch.float64, out_transfer_dtype=torch.float64)
@@ -239,6 +249,58 @@ def test_d64_n1e4_k64_full_size(H, prec):
     say(f"  rel err vs oracle {err:.3e}")
     assert same == 126
     assert err <= (FP64_TOL_CUT_AT_NOISE if prec == 0 else MIXED_TOL)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_d64_n1e4_k64_fixed_r64(H, prec, d64):
+    """The same workload truncated to fixed rank 64: no rank decision sits at
+    the rounding level, so the float64 path is held to the 1e-10 gate."""
+    say(f"case d64_n1e4_k64 full size fixed r=64 prec={prec}")
+    import torch
+    T, _ = O.truncate(d64["X"], mode="fixed", ranks=[64] * 127)
+    devs = [H.DeviceHT.from_input(d64["a"]), H.DeviceHT.from_input(d64["c"])]
+    tr = H.Truncator(devs, [1.0, 1.0], mode=H.HT_RANK_FIXED, ranks=[64] * 127, precision=prec,
+                     out_frame_dtype=torch.float64, out_transfer_dtype=torch.float64)
+    res = tr()
+    torch.cuda.synchronize()
+    err = O.rel_diff(to_oracle(res.out), T)
+    say(f"  rel err vs oracle {err:.3e} flags {res.flags}")
+    assert res.ranks[1:] == [64] * 126
+    assert err <= (FP64_TOL if prec == 0 else MIXED_TOL)
+
+
+def test_entries_full_size_rank128(H, d64):
+    """ht_entries on the materialised d=64, n=1e4 sum (rank 128 at every
+    node): 2e5 indices span 13 chunks of the level-wise evaluation (the last
+    one ragged) with Khatri-Rao reductions of 128 x 128 = 16384; every 97th
+    index is checked against the oracle's eq. (transfermult) recursion."""
+    say("case entries d=64 n=1e4 rank 128, m=2e5")
+    import torch
+    da, dc = H.DeviceHT.from_input(d64["a"]), H.DeviceHT.from_input(d64["c"])
+    Sd = H.ht_add(da, dc, 1.0, 1.0)
+    idx = S.entry_indices(200000, 64, 10000, seed=606)
+    got = H.ht_entries(Sd, torch.from_numpy(idx)).cpu().numpy()
+    sub = np.arange(0, idx.shape[0], 97)
+    ref = O.entries(d64["X"], idx[sub])
+    rel = np.linalg.norm(got[sub] - ref) / np.linalg.norm(ref)
+    say(f"  sampled relative 2-norm error {rel:.3e} over {sub.size} indices")
+    assert rel <= 1e-12
+    np.testing.assert_allclose(got[sub], ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_input_flagged(H, bad):
+    """A NaN or Inf in a leaf frame is reported in the flags word
+    (HT_FLAG_NONFINITE); the call still completes."""
+    say(f"case non-finite input {bad}")
+    a, c = S.workload_pair("d4_n16_k4")
+    A, C = O.from_input(a), O.from_input(c)
+    A.U[2] = A.U[2].copy()
+    A.U[2][5, 1] = bad
+    res = run_trunc(H, [A, C], [1.0, 1.0], 0, H.HT_RANK_FIXED, ranks=[4] * 7)
+    say(f"  flags {res.flags:#x}")
+    assert res.flags & H.HT_FLAG_NONFINITE
 
 
 # ------------------------------------------------------------------ edge cases
