@@ -198,6 +198,31 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
                       int64_t* out_log2_scale, uint32_t* flags, double* out_sigma,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- truncation without allocation
+ * For callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same operation,
+ * arguments, results and errors as ht_truncate, without the workspace: the
+ * workspace and the launch tables live in a static device array of
+ * HT_NOALLOC_SCRATCH_BYTES per GPU (the first 2 MiB hold the tables), which
+ * every GPU the library runs on holds until the process ends.
+ * ht_create_context() looks up the array's address on its device once.
+ * The call allocates nothing (no hipMalloc or hipFree, no stream or event is
+ * created; the whole tree runs on `stream`, and profiling takes no events
+ * here).  Its launch tables are copied from host memory with hipMemcpyAsync
+ * on `stream` unless the array already holds the same tables from the
+ * previous call on this GPU.  The array keeps the last call's contents; every
+ * call clears what it needs zeroed itself.  All calls on one GPU share the
+ * array: calls that may overlap on the device (other streams or contexts
+ * without ordering between them) race; calls on one stream are ordered.
+ * Errors: as ht_truncate; HT_EWORKSPACE when the truncation needs more than
+ * HT_NOALLOC_SCRATCH_BYTES - 2 MiB of workspace (ht_truncate_workspace gives
+ * the figure) or more than 2 MiB of tables; HT_EUNSUPPORTED for device ids
+ * above 63. */
+#define HT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ht_status ht_truncate_noalloc(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
+                              const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
+                              int64_t* out_log2_scale, uint32_t* flags, double* out_sigma, void* stream);
+
 /* ---------------------------------------------------------------- batched truncation
  * Truncates `count` independent lazy sums in one pass: problem c is the sum of
  * X[o_c .. o_c + n_in[c]) (o_c = n_in[0] + .. + n_in[c-1]) with coefficients

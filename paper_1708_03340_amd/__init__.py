@@ -22,12 +22,13 @@ HT_PREC_FP64, HT_PREC_MIXED = 0, 1
 HT_RANK_FIXED, HT_RANK_TOL = 0, 1
 HT_FLAG_RANK_DEFICIENT, HT_FLAG_NONFINITE, HT_FLAG_CAPPED, HT_FLAG_NOCONV = 1, 2, 4, 8
 KMAX = 128
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HT_NOALLOC_SCRATCH_BYTES
 
 EXPORTS = [
     "ht_create_context", "ht_destroy_context", "ht_status_string", "ht_last_error", "ht_version",
     "ht_tree", "ht_add", "ht_orthogonalize_workspace", "ht_orthogonalize", "ht_gramians_workspace",
     "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_truncate_batched_workspace",
-    "ht_truncate_batched", "ht_entries_workspace", "ht_entries",
+    "ht_truncate_batched", "ht_entries_workspace", "ht_entries", "ht_truncate_noalloc",
     "ht_profile_enable", "ht_profile_read", "ht_profile_reset",
 ]
 
@@ -100,6 +101,8 @@ def lib(path: Optional[str] = None):
     L.ht_truncate_workspace.argtypes = [VP, P(HtDesc), I32, P(HtTruncOpts), P(ctypes.c_size_t)]
     L.ht_truncate.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, P(HtTruncOpts), P(HtDesc), VP, VP, VP,
                               VP, VP, ctypes.c_size_t, VP]
+    L.ht_truncate_noalloc.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, P(HtTruncOpts), P(HtDesc), VP,
+                                      VP, VP, VP, VP]
     L.ht_truncate_batched_workspace.argtypes = [VP, I32, P(HtDesc), P(I32), P(HtTruncOpts), P(ctypes.c_size_t)]
     L.ht_truncate_batched.argtypes = [VP, I32, P(HtDesc), P(I32), P(ctypes.c_double), P(HtTruncOpts), P(HtDesc),
                                       P(VP), VP, VP, P(VP), VP, ctypes.c_size_t, VP]
@@ -406,9 +409,10 @@ class Truncator:
 
     def __init__(self, Xs: Sequence[DeviceHT], coef=None, *, mode=HT_RANK_FIXED, ranks=None, eps=0.0,
                  relative=True, max_rank=0, precision=HT_PREC_MIXED, out_frame_dtype=None,
-                 out_transfer_dtype=None, want_sigma=False, ctx=None):
+                 out_transfer_dtype=None, want_sigma=False, noalloc=False, ctx=None):
         import torch
         self.ctx = ctx or ht_create_context()
+        self.noalloc = bool(noalloc)   # ht_truncate_noalloc: no workspace, the library's static scratch
         self.Xs = list(Xs)
         d = Xs[0].d
         nn = 2 * d - 1
@@ -425,7 +429,7 @@ class Truncator:
         need = ctypes.c_size_t(0)
         _check(lib().ht_truncate_workspace(self.ctx.h, self.xdescs, len(Xs), ctypes.byref(self.opts),
                                            ctypes.byref(need)))
-        self.ws = _ws(need.value)
+        self.ws = None if self.noalloc else _ws(need.value)
         self.ws_bytes = need.value
         self.ranks = torch.zeros(nn, dtype=torch.int32, device="cuda")
         self.scale = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -434,9 +438,16 @@ class Truncator:
         self.odesc = self.out.desc()
 
     def __call__(self, stream=None):
-        _check(lib().ht_truncate(self.ctx.h, self.xdescs, self.coef, len(self.Xs), ctypes.byref(self.opts),
-                                 ctypes.byref(self.odesc), _ptr(self.ranks), _ptr(self.scale), _ptr(self.flags),
-                                 _ptr(self.sigma), _ptr(self.ws), self.ws_bytes, _stream_ptr(stream)))
+        if self.noalloc:
+            _check(lib().ht_truncate_noalloc(self.ctx.h, self.xdescs, self.coef, len(self.Xs),
+                                             ctypes.byref(self.opts), ctypes.byref(self.odesc), _ptr(self.ranks),
+                                             _ptr(self.scale), _ptr(self.flags), _ptr(self.sigma),
+                                             _stream_ptr(stream)))
+        else:
+            _check(lib().ht_truncate(self.ctx.h, self.xdescs, self.coef, len(self.Xs), ctypes.byref(self.opts),
+                                     ctypes.byref(self.odesc), _ptr(self.ranks), _ptr(self.scale),
+                                     _ptr(self.flags), _ptr(self.sigma), _ptr(self.ws), self.ws_bytes,
+                                     _stream_ptr(stream)))
         self.out.log2_scale = self.scale
         return TruncResult(self.out, self.ranks, self.scale, self.flags, self.sigma)
 

@@ -704,7 +704,7 @@ namespace {
 
 const size_t kCacheMax = 24;
 
-ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream);
+ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream, bool allow_prof = true);
 
 ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
   build_key(P);
@@ -740,9 +740,11 @@ ht_status run_plan(ht_context* ctx, Plan& P, hipStream_t stream) {
   return launch_plan(ctx, P, dtable, stream);
 }
 
-// Enqueues the launches of a plan whose argument table is at dtable.
-ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream) {
+// Enqueues the launches of a plan whose argument table is at dtable.  With
+// allow_prof false no timing events are taken, even when profiling is on.
+ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t stream, bool allow_prof) {
   char* tb = reinterpret_cast<char*>(dtable);
+  const bool prof = ctx->prof && allow_prof;
   bool forks = false;
   for (const auto& op : P.ops) forks = forks || op.kind == OP_FORK;
   std::unique_lock<std::mutex> run_lk;
@@ -768,7 +770,7 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
     if (op.stream) stream = ctx->side;
     hipError_t e = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx->prof) {
+    if (prof) {
       ev0 = take_event(ctx);
       ev1 = take_event(ctx);
       if (ev0) (void)hipEventRecord(ev0, stream);
@@ -829,7 +831,7 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
         break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
-    if (ctx->prof && ev0 && ev1) {
+    if (prof && ev0 && ev1) {
       (void)hipEventRecord(ev1, stream);
       const std::string kn = kernel_name(op);
       ctx->pending.push_back({ev0, ev1, (op.label && *op.label) ? op.label : "other", kn, op.flops, op.bytes_alg});
@@ -1439,6 +1441,38 @@ void plan_gramians(Plan& P, const Tree& tr, const std::vector<int>& K, std::vect
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Workspace and launch tables of ht_truncate_noalloc: one array per GPU,
+// loaded with the library's code object and held until the process ends.
+// In host code `scratch` names a host-side stand-in; kernels only ever get
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[HT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr size_t kNoAllocTableBytes = size_t(2) << 20;   // launch tables at the front
+constexpr int kNoAllocDevices = 64;
+struct NoAllocDevice {
+  std::mutex mu;                        // one enqueue at a time on this GPU
+  void* ptr = nullptr;                  // device address of `scratch` on this GPU
+  std::vector<unsigned char> table;     // the table image last copied to the array
+};
+NoAllocDevice g_noalloc[kNoAllocDevices];
+
+// Looks up this device's copy of the array (device must be current).
+ht_status noalloc_setup(int device) {
+  if (device < 0 || device >= kNoAllocDevices) return HT_OK;   // the entry point reports it
+  NoAllocDevice& nd = g_noalloc[device];
+  std::lock_guard<std::mutex> lk(nd.mu);
+  if (nd.ptr) return HT_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(HT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  nd.ptr = p;
+  return HT_OK;
+}
+}  // namespace
+
 // ================================================================== ABI
 extern "C" {
 
@@ -1463,6 +1497,12 @@ ht_status ht_create_context(int device, ht_context** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
     return fail(HT_EDEVICE, "no such HIP device");
+  int prev = 0;
+  HT_HIP(hipGetDevice(&prev));
+  HT_HIP(hipSetDevice(device));
+  const ht_status st = noalloc_setup(device);
+  (void)hipSetDevice(prev);
+  if (st) return st;
   ht_context* c = new ht_context();
   c->device = device;
   *out = c;
@@ -1783,6 +1823,46 @@ ht_status ht_truncate(ht_context* ctx, const ht_desc* X, const double* coef, int
                       nullptr);
   if (st) return st;
   return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+ht_status ht_truncate_noalloc(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in,
+                              const ht_trunc_opts* opts, const ht_desc* out, int32_t* out_ranks,
+                              int64_t* out_log2_scale, uint32_t* flags, double* out_sigma, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  if (ctx->device < 0 || ctx->device >= kNoAllocDevices)
+    return fail(HT_EUNSUPPORTED, "ht_truncate_noalloc: device ids above 63 have no static scratch");
+  NoAllocDevice& nd = g_noalloc[ctx->device];
+  if (!nd.ptr) return fail(HT_EDEVICE, "ht_truncate_noalloc: the context was not set up on its device");
+  size_t need = 0;
+  ht_status st = ht_truncate_workspace(ctx, X, n_in, opts, &need);
+  if (st) return st;
+  const size_t ws_max = HT_NOALLOC_SCRATCH_BYTES - kNoAllocTableBytes;
+  if (need > ws_max)
+    return fail(HT_EWORKSPACE, "ht_truncate_noalloc: this truncation needs " + std::to_string(need) +
+                                   " bytes of workspace; the static scratch holds " + std::to_string(ws_max));
+  HT_HIP(hipSetDevice(ctx->device));
+  char* base = reinterpret_cast<char*>(nd.ptr);
+  Plan P;
+  // one stream only: the second stream and its events would be created on first use
+  st = build_truncate(ctx, X, coef, n_in, opts, out, out_ranks, out_log2_scale, flags, out_sigma,
+                      base + kNoAllocTableBytes, P, nullptr, /*overlap=*/false);
+  if (st) return st;
+  if (P.table.size() > kNoAllocTableBytes)
+    return fail(HT_EWORKSPACE, "ht_truncate_noalloc: launch tables of " + std::to_string(P.table.size()) +
+                                   " bytes exceed the " + std::to_string(kNoAllocTableBytes) + " reserved");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(nd.mu);
+  // Stream-ordered copy of the tables from host memory (pageable: the runtime
+  // stages it before returning); skipped when the array already holds them.
+  if (!P.table.empty() && P.table != nd.table) {
+    nd.table = P.table;
+    const hipError_t e = hipMemcpyAsync(base, nd.table.data(), nd.table.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      nd.table.clear();
+      return fail(HT_EDEVICE, std::string("ht_truncate_noalloc: table copy: ") + hipGetErrorString(e));
+    }
+  }
+  return launch_plan(ctx, P, base, s, /*allow_prof=*/false);
 }
 
 // ------------------------------------------------------------------ batched truncation
