@@ -136,8 +136,6 @@ size_t put(Plan& P, const std::vector<T>& v) {
 
 int esize(int t) { return t == F32 ? 4 : 8; }
 
-// Eigensolver scratch: the Householder reflectors (K x K) and their tau (K).
-size_t eig_scratch_doubles(int K) { return (size_t)K * K + (size_t)K + 64; }
 
 GemmDesc blank_desc() {
   GemmDesc d;
@@ -2628,7 +2626,7 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
             return s;
         } else if (op.kind == OP_EIG) {
           if ((s = chk(a.Bh, kk, 8, "Bh")) || (s = chk(a.Q, kk, 8, "Q")) || (s = chk(a.lam, a.K, 8, "lam")) ||
-              (s = chk(a.scratch, kk + a.K, 8, "scratch")))
+              (s = chk(a.scratch, eig_scratch_doubles(a.K), 8, "scratch")))
             return s;
         } else if (op.kind == OP_RANK) {
           if ((s = chk(a.lam, a.K, 8, "lam")) || (s = chk(a.rank_dev, 1, 4, "rank"))) return s;

@@ -7,33 +7,37 @@
 //     along the 16 lanes of a row group, and applies the rank-2 update in
 //     registers: three barriers per step.  The reflectors go to the node's
 //     scratch.
-//  2. Implicit QL iterations with Wilkinson shifts on T, pipelined: wave 0
-//     finds the next unreduced block and runs the chain of plane rotations of
-//     the next sweep (one lane; rotation from a reciprocal square root refined
-//     by one third-order step), while waves 1-3 apply the previous sweep to
-//     the rows of Z in LDS.  One barrier per sweep.  A tridiagonal graded
-//     large-at-the-top is reversed first (T' = P T P, Z starts as P): QL keeps
-//     the relative accuracy of small eigenvalues only when the matrix grows
-//     toward the bottom, and the Gramians next to the root are graded the
-//     other way.
+//  2. Divide and conquer on T (Cuppen's tearing), all merges of one depth of
+//     the halving tree at once.  T, scaled to max-norm 1, is torn at every
+//     row boundary: T = diag(T_1, T_2) + rho v v^T with v = e_m + sign(b) e_m+1,
+//     rho = |b|, so the blocks start as single rows d_i - |e_i-1| - |e_i|.  A
+//     merge of two blocks with eigen-decompositions Q_j D_j Q_j^T solves the
+//     rank-one update D + rho z z^T, z = Q^T v / sqrt(2) (rho doubled):
+//       - the eigenvalues are sorted; entries with rho |z_j| below
+//         2 u max|D| of the block, and pairs of poles closer than that after a
+//         plane rotation of their z entries, deflate (one wave per merge runs
+//         the scan, its lanes rotate the two eigenvector columns);
+//       - each remaining root of 1 + rho sum_j z_j^2 / (d_j - lambda) = 0 is
+//         found by one thread: origin at the nearer pole, a start from the
+//         two nearest poles with the other terms frozen at the midpoint, then
+//         the two-pole model matching psi, psi' and phi, phi' (Bunch, Nielsen
+//         and Sorensen), bracketed by bisection;
+//       - z is recomputed from the roots (Gu and Eisenstat), which makes the
+//         vectors z_j / (d_j - lambda_i) orthogonal to working precision;
+//       - the merged block's eigenvectors are the product of the two blocks'
+//         eigenvectors (Z in LDS) with those vectors (written to scratch),
+//         eight by eight outputs per thread, columns in ascending order.
 //  3. Back-transformation Q = H_0 ... H_{K-3} Z with Z in registers, the 16
 //     lanes of a DPP row holding the rows of a column strip: no barriers.
 //  4. Eigenvalues sorted descending (clipped at 0) with their columns.
-// Q is a product of reflectors and rotations, orthogonal to working precision.
+// Q is a product of reflectors, plane rotations and the merge products,
+// orthogonal to working precision.
 #include "dense_util.h"
 
 namespace ht {
 namespace {
 
 constexpr int NT = DNT;
-
-// 1 / sqrt(x), x > 0 normal: hardware estimate (relative error ~5e-8) and one
-// third-order step, y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt3(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * y, y, 1.0);
-  return fma(y * e, fma(0.375, e, 0.5), y);
-}
 
 // Sum over a wave of 64 lanes, returned to every lane: DPP sums in rows of
 // 16, then the four row sums.
@@ -42,30 +46,122 @@ __device__ __forceinline__ double wave_sum(double v) {
   return ((lane_val(v, 0) + lane_val(v, 16)) + lane_val(v, 32)) + lane_val(v, 48);
 }
 
-enum : int { SWEEP_NONE = 0, SWEEP_ROT = 1, SWEEP_DONE = 2 };
+constexpr double kUnit = 1.1102230246251565e-16;   // unit roundoff of float64
+
+// Root x in (Alo, Ahi) of c + b1 / (Alo - x) + b2 / (Ahi - x) = 0, where one
+// of Alo, Ahi is zero (the origin pole) and b1, b2 > 0.  Mirrored so that the
+// origin is the lower pole, then the smaller root of the quadratic in its
+// cancellation-free form.  Not finite when the model has no such root.
+__device__ __forceinline__ double dc_quad(double c, double b1, double b2, double Alo, double Ahi) {
+  const bool low = Alo == 0.0;
+  const double cc = low ? c : -c, p1 = low ? b1 : b2, p2 = low ? b2 : b1, W = low ? Ahi : -Alo;
+  const double B = -(cc * W + p1 + p2), C = p1 * W;
+  const double sq = sqrt(fmax(fma(B, B, -4.0 * cc * C), 0.0));
+  const double y = -B >= 0.0 ? 2.0 * C / (-B + sq) : (-B - sq) / (2.0 * cc);
+  return low ? y : -y;
+}
+
+// Root i of the secular equation 1 + rho sum_j z_j^2 / (d_j - lambda) = 0
+// for poles d[0] < ... < d[nk-1] (the root lies in (d_i, d_i+1), the last
+// one in (d_nk-1, d_nk-1 + rho |z|^2]).  Returns lambda = d[org] + tau with
+// the origin pole org and the offset tau (so d_j - lambda is formed as
+// (d_j - d_org) - tau, without cancellation).  *iters: iterations taken;
+// *conv: false if the iteration limit was reached.
+__device__ void dc_root(int i, int nk, const double* d, const double* z, double rho, int* org_out,
+                        double* tau_out, int* iters, bool* conv) {
+  int org;
+  double lo_t, hi_t, tau;
+  if (i < nk - 1) {
+    const double di = d[i], hw = 0.5 * (d[i + 1] - di);
+    double f = 1.0;
+    for (int j = 0; j < nk; ++j) {
+      const double del = (d[j] - di) - hw;
+      f += rho * z[j] * z[j] * rcp_nr(del);
+    }
+    const double wi = rho * z[i] * z[i], wi1 = rho * z[i + 1] * z[i + 1];
+    const double ti = wi * rcp_nr(-hw), ti1 = wi1 * rcp_nr((d[i + 1] - di) - hw);
+    if (f >= 0.0) {
+      org = i; lo_t = 0.0; hi_t = hw; tau = hw;
+    } else {
+      org = i + 1; lo_t = -hw; hi_t = 0.0; tau = -hw;
+    }
+    // the two nearest poles with their own weights, the rest frozen
+    const double x0 = dc_quad(f - ti - ti1, wi, wi1, d[i] - d[org], d[i + 1] - d[org]);
+    if (lo_t < x0 && x0 < hi_t) tau = x0;
+  } else {
+    double zz = 0.0;
+    for (int j = 0; j < nk; ++j) zz += z[j] * z[j];
+    org = nk - 1; lo_t = 0.0; hi_t = rho * zz; tau = hi_t;
+  }
+  const double dorg = d[org];
+  const double Alo = d[i] - dorg, Ahi = i + 1 < nk ? d[i + 1] - dorg : 0.0;
+  int it = 0;
+  bool ok = false;
+  for (; it < 64; ++it) {
+    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, sabs = 0.0;
+    for (int j = 0; j < nk; ++j) {
+      const double inv = rcp_nr((d[j] - dorg) - tau);
+      const double tj = rho * z[j] * z[j] * inv, dtj = tj * inv;
+      if (j <= i) { psi += tj; dpsi += dtj; } else { phi += tj; dphi += dtj; }
+      sabs += fabs(tj);
+    }
+    const double f = 1.0 + psi + phi;
+    if (fabs(f) <= kUnit * (8.0 * (1.0 + sabs) + fabs(tau) * (dpsi + dphi))) { ok = true; break; }
+    if (f > 0.0) hi_t = tau; else lo_t = tau;
+    const double dlo = Alo - tau;
+    const double b1 = dpsi * dlo * dlo, a1 = psi - b1 / dlo;
+    double x;
+    if (i < nk - 1) {
+      const double dhi = Ahi - tau;
+      const double b2 = dphi * dhi * dhi, a2 = phi - b2 / dhi;
+      x = dc_quad(1.0 + a1 + a2, b1, b2, Alo, Ahi);
+    } else {
+      const double c = 1.0 + a1;
+      x = c > 0.0 ? b1 / c : hi_t + 1.0;   // no model root: bisect
+    }
+    if (!(lo_t < x && x < hi_t)) {
+      x = 0.5 * (lo_t + hi_t);
+      if (!(lo_t < x && x < hi_t)) { ok = true; break; }   // bracket down to adjacent doubles
+    }
+    if (x == tau) { ok = true; break; }
+    tau = x;
+  }
+  *org_out = org;
+  *tau_out = tau;
+  *iters = it;
+  *conv = ok;
+}
 
 // KT: the largest order the instantiation takes (64, 96 or 128).  Up to 96 a
-// node's LDS is at most 80 KB and two nodes share a CU (the registers of the
-// rotation blocks keep it from more).
+// node's LDS is at most 80 KB and two nodes share a CU.
 template <int KT>
 __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallArgs* __restrict__ args,
                                                                    GlobalState* st) {
   constexpr int RB = KT / 16;                    // row (column) blocks of 16
-  __shared__ double L[KT * (KT + 1)];            // Z during the QL phase (column K: store sink)
-  __shared__ double dg[KT], eo[KT];
-  // the vectors of the tridiagonalisation and, later, the rotations of two
-  // QL sweeps share one buffer
+  constexpr int PADC = KT > 96 ? 1 : 0;          // row padding of Z (LDS permitting)
+  __shared__ double L[KT * (KT + PADC)];         // Z, rows of the tridiagonal basis
+  __shared__ double dg[KT], eo[KT];              // diagonal (later: eigenvalues), off-diagonal
+  // the vectors of the tridiagonalisation, then four per-position arrays of
+  // the merges: sorted eigenvalues (compacted to the kept poles), their z
+  // entries, the new eigenvalue of each position, the root offsets
   __shared__ double vbuf[4 * KT];
   double* const xs = vbuf;
   double* const ps = vbuf + KT;
-  double (*const rcs)[KT] = reinterpret_cast<double (*)[KT]>(vbuf);
-  double (*const rss)[KT] = reinterpret_cast<double (*)[KT]>(vbuf + 2 * KT);
-  __shared__ int sw_state[2], sw_m[2], sw_lo[2];
-  __shared__ double part[16];
-  __shared__ int rankpos[KT];
+  double* const part = vbuf + 2 * KT;            // 16 partial sums
+  double* const ds = vbuf;
+  double* const zs = vbuf + KT;
+  double* const nv = vbuf + 2 * KT;
+  double* const taus = vbuf + 3 * KT;
+  __shared__ double zh[KT];                      // recomputed z of the kept poles
+  // per position of a merged block: child column in sorted order; kept
+  // position of kept index j; kept index of a position (255: deflated);
+  // origin pole of root i; new column of a position (later: sort rank)
+  __shared__ unsigned char perm[KT], kidx[KT], jof[KT], orgs[KT], newcol[KT];
+  __shared__ unsigned char kcnt[64];             // kept poles per merge of a depth
+  __shared__ int sh_maxit, sh_noconv;
   const SmallArgs& a = args[blockIdx.x];
   if (a.st) st = a.st;
-  const int K = a.K, ld = K + 1;
+  const int K = a.K, ld = K + PADC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ty = tid >> 4, tx = tid & 15;
   double* Vs = a.scratch;                 // reflector k: Vs[k*K + i], i < K-k-1
@@ -168,213 +264,257 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       }
     if (tid == 0) {
       eo[K - 1] = 0.0;
-      sw_state[0] = sw_state[1] = SWEEP_NONE;
+      sh_maxit = 0;
+      sh_noconv = 0;
     }
-  }
-  __syncthreads();
-  const bool rev = K > 1 && fabs(dg[0]) > fabs(dg[K - 1]);
-  double dtmp = 0.0, etmp = 0.0;
-  if (rev) {
-    if (tid < K) dtmp = dg[K - 1 - tid];
-    if (tid < K - 1) etmp = eo[K - 2 - tid];
-  }
-  __syncthreads();
-  if (rev) {
-    if (tid < K) dg[tid] = dtmp;
-    if (tid < K - 1) eo[tid] = etmp;
-  }
-  for (int i = tid; i < K * K; i += NT) {
-    const int r = i / K, c = i % K;
-    L[r * ld + c] = (rev ? (r + c == K - 1) : (r == c)) ? 1.0 : 0.0;
   }
   __syncthreads();
 
-  // ---- 2. implicit QL on (dg, eo), eo[i] couples i and i+1.  e_m deflates
-  // below u (|d_m| + |d_m+1|) or below 1e-18 ||T|| (the rounding level of the
-  // Gramian, which moves no eigenvalue by more than that)
-  double tloc = 0.0;
-  if (wave == 0)
-    for (int i = lane; i < K; i += 64) tloc = fmax(tloc, fabs(dg[i]) + fabs(eo[i]));
-  for (int off = 32; off > 0; off >>= 1) tloc = fmax(tloc, __shfl_xor(tloc, off, 64));
-  const double abs_tol = 1e-18 * tloc;   // used by wave 0 only
-  int l = 0, iter = 0;                   // producer state (wave 0)
-  int max_it = 0;                        // most sweeps any one eigenvalue took (wave 0)
-  bool noconv = false;                   // an eigenvalue was given up on (wave 0)
-  // Finds the next sweep and writes its rotations into buffer b (wave 0 only).
-  auto produce = [&](int b) {
-    while (true) {
-      if (l >= K) {
-        if (lane == 0) sw_state[b] = SWEEP_DONE;
-        return;
+  // ---- 2. divide and conquer on (dg, eo); eo[i] couples rows i and i+1
+  {
+    double amax = 0.0;
+    for (int i = tid; i < K; i += NT) amax = fmax(amax, fmax(fabs(dg[i]), fabs(eo[i])));
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) zh[wave] = amax;
+    __syncthreads();
+    const double scale = fmax(fmax(zh[0], zh[1]), fmax(zh[2], zh[3]));
+    // Z = I; single rows d_i - |e_i-1| - |e_i| (all scaled by 1 / scale)
+    for (int i = tid; i < K * ld; i += NT) L[i] = (i / ld == i % ld) ? 1.0 : 0.0;
+    const bool run = K >= 2 && scale > 0.0 && isfinite(scale);
+    const double inv = run ? 1.0 / scale : 1.0;
+    if (run && tid < K) {
+      const double em = tid > 0 ? fabs(eo[tid - 1]) : 0.0, ep = tid < K - 1 ? fabs(eo[tid]) : 0.0;
+      dg[tid] = (dg[tid] * inv - em * inv) - ep * inv;
+    }
+    __syncthreads();
+    if (run && tid < K) eo[tid] *= inv;
+    __syncthreads();
+    const int T = run ? dc_depths(K) : 0;
+    int64_t vbase = eig_reflector_doubles(K);
+    double* const scr = a.scratch;
+    for (int t = T - 1; t >= 0; --t) {
+      const int M = ((K - 1) >> t) + 1;          // rows of the largest block at this depth
+      // the merge of position x (tid): block b of depth t
+      const int x = tid;
+      int b = 0, lo = 0, mid = 0, hi = 0;
+      bool mine = false;
+      if (x < K) {
+        b = (((x + 1) << t) + K - 1) / K - 1;
+        lo = (b * K) >> t;
+        hi = ((b + 1) * K) >> t;
+        mid = ((2 * b + 1) * K) >> (t + 1);
+        mine = lo < mid && mid < hi;
       }
-      int m = K - 1;
-      for (int base = l; base < K - 1; base += 64) {
-        const int idx = base + lane;
-        bool neg = false;
-        if (idx < K - 1) {
-          const double e = fabs(eo[idx]);
-          neg = e <= 2.2e-16 * (fabs(dg[idx]) + fabs(dg[idx + 1])) || e <= abs_tol;
+      const int m = hi - lo;
+      const double rho = mine ? 2.0 * fabs(eo[mid - 1]) : 0.0;
+
+      // (a) sort the two blocks' eigenvalues; z = Q^T v / sqrt(2)
+      if (mine) {
+        const double v = dg[x];
+        int r = 0;
+        for (int y = lo; y < hi; ++y) {
+          const double w = dg[y];
+          r += (w < v || (w == v && y < x)) ? 1 : 0;
         }
-        const unsigned long long bal = __ballot(neg);
-        if (bal) {
-          m = base + __ffsll((long long)bal) - 1;
-          break;
-        }
+        r = min(r, m - 1);
+        const double sgn = eo[mid - 1] >= 0.0 ? 1.0 : -1.0;
+        const double zx = (x < mid ? L[(mid - 1) * ld + x] : sgn * L[mid * ld + x]) * 0.70710678118654752;
+        perm[lo + r] = (unsigned char)x;
+        ds[lo + r] = v;
+        zs[lo + r] = zx;
       }
-      if (m == l || iter >= 80) {   // converged (or given up on): next eigenvalue
-        max_it = max(max_it, iter);
-        if (m != l) noconv = true;   // 80 sweeps without e[l] reaching the deflation test
-        ++l;
-        iter = 0;
-        continue;
-      }
-      ++iter;
-      if (lane == 0) {
-        double g = (dg[l + 1] - dg[l]) / (2.0 * eo[l]);
-        double r = sqrt(g * g + 1.0);
-        g = dg[m] - dg[l] + eo[l] / (g + (g >= 0.0 ? r : -r));
-        double sn = 1.0, cs = 1.0, p = 0.0;
-        double d_i1 = dg[m];                 // d[i+1] for i = m-1
-        // rotations i = m-1 .. l.  Whole blocks of eight run as straight-line
-        // code: their operands (e[i], d[i]) are loaded one block ahead and
-        // their results (e[i+1], d[i+1], c_i, s_i) stored after the block, so
-        // neither an LDS access nor a branch sits on the dependent chain.  A
-        // block in which a rotation meets f = g = 0 (a split) is redone
-        // rotation by rotation, as is the tail of fewer than eight.
-        int lo = l;
-        bool split = false;
-        // one rotation with the split test; false on a split at index i
-        auto step = [&](int i, double e_i, double d_i) -> bool {
-          const double f = sn * e_i, bb = cs * e_i;
-          const double x2 = f * f + g * g;
-          if (x2 == 0.0) {  // split: restart on the smaller block
-            eo[i + 1] = 0.0;
-            dg[i + 1] = d_i1 - p;
-            lo = i + 1;
-            return false;
+      __syncthreads();
+
+      // (b) deflation: one wave per merge scans the sorted entries, its lanes
+      // rotate eigenvector columns; kept poles are compacted in place
+      for (int bb = wave; bb < (1 << t); bb += NT / 64) {
+        const int blo = (bb * K) >> t, bhi = ((bb + 1) * K) >> t, bmid = ((2 * bb + 1) * K) >> (t + 1);
+        if (!(blo < bmid && bmid < bhi)) continue;
+        const int bm = bhi - blo;
+        const double brho = 2.0 * fabs(eo[bmid - 1]);
+        const double tol = 2.0 * kUnit * fmax(fabs(ds[blo]), fabs(ds[bhi - 1]));
+        int nk = 0, pk = -1;
+        for (int p = 0; p < bm; ++p) {
+          const int P = blo + p;
+          const double zp = zs[P], dp = ds[P];
+          if (brho * fabs(zp) <= tol) {
+            if (lane == 0) { nv[P] = dp; jof[P] = 255; }
+            continue;
           }
-          const double ir = rsqrt3(x2);
-          eo[i + 1] = x2 * ir;
-          sn = f * ir;
-          cs = g * ir;
-          g = d_i1 - p;
-          r = (d_i - g) * sn + 2.0 * cs * bb;
-          p = sn * r;
-          dg[i + 1] = g + p;
-          g = cs * r - bb;
-          rcs[b][i] = cs;
-          rss[b][i] = sn;
-          d_i1 = d_i;
-          return true;
-        };
-        // Rotation u of a block consumes the operands (eb[u], db[u]) and at
-        // once loads those of rotation u of the next block into the same
-        // registers, so the loop carries no copies.  A block that meets
-        // x2 = 0 ends with g and p not finite (the reciprocal square root of
-        // zero turns every later quantity into NaN); it is redone rotation by
-        // rotation from its operands in LDS, unchanged until its results are
-        // stored.
-        double eb[8], db[8];
+          if (pk >= 0) {
+            const int PK = blo + pk;
+            const double zq = zs[PK], dq = ds[PK];
+            const double tau = sqrt(fma(zq, zq, zp * zp));
+            const double c = zp / tau, sn = -zq / tau;
+            if (fabs((dp - dq) * c * sn) <= tol) {
+              // rotate so that z_pk = 0: position pk deflates
+              const int ca = perm[PK], cb = perm[P];
+              for (int r = blo + lane; r < bhi; r += 64) {
+                const double u = L[r * ld + ca], w = L[r * ld + cb];
+                L[r * ld + ca] = c * u + sn * w;
+                L[r * ld + cb] = c * w - sn * u;
+              }
+              if (lane == 0) {
+                zs[P] = tau;
+                nv[PK] = dq * c * c + dp * sn * sn;
+                jof[PK] = 255;
+                ds[P] = dq * sn * sn + dp * c * c;
+              }
+            } else {
+              if (lane == 0) {
+                kidx[blo + nk] = (unsigned char)pk;
+                jof[PK] = (unsigned char)nk;
+                ds[blo + nk] = dq;
+                zs[blo + nk] = zq;
+              }
+              ++nk;
+            }
+          }
+          pk = p;
+        }
+        if (pk >= 0) {
+          const int PK = blo + pk;
+          const double dq = ds[PK], zq = zs[PK];
+          if (lane == 0) {
+            kidx[blo + nk] = (unsigned char)pk;
+            jof[PK] = (unsigned char)nk;
+            ds[blo + nk] = dq;
+            zs[blo + nk] = zq;
+          }
+          ++nk;
+        }
+        if (lane == 0) kcnt[bb] = (unsigned char)nk;
+      }
+      __syncthreads();
+
+      // (c) one thread per root of the secular equation
+      const int nk = mine ? kcnt[b] : 0;
+      const int i = x - lo;
+      if (mine && i < nk) {
+        int org, its;
+        double tau;
+        bool conv;
+        dc_root(i, nk, ds + lo, zs + lo, rho, &org, &tau, &its, &conv);
+        orgs[x] = (unsigned char)org;
+        taus[x] = tau;
+        nv[lo + kidx[x]] = ds[lo + org] + tau;
+        atomicMax(&sh_maxit, its);
+        if (!conv) sh_noconv = 1;
+      }
+      __syncthreads();
+
+      // (d) z recomputed from the roots (kept index j = i); new column of
+      // every position: rank of its new eigenvalue in the block
+      if (mine) {
+        const double* d = ds + lo;
+        if (i < nk) {
+          const double dj = d[i];
+          double w = (taus[x] - (dj - d[orgs[x]])) / rho;   // (lambda_j - d_j) / rho
+          for (int q = 0; q < nk; ++q) {
+            if (q == i) continue;
+            const double lq = (d[orgs[lo + q]] - dj) + taus[lo + q];   // lambda_q - d_j
+            w *= lq * rcp_nr(d[q] - dj);
+          }
+          zh[x] = copysign(sqrt(fmax(w, 0.0)), zs[x]);
+        }
+        const double v = nv[x];
+        int r = 0;
+        for (int y = lo; y < hi; ++y) {
+          const double u = nv[y];
+          r += (u < v || (u == v && y < x)) ? 1 : 0;
+        }
+        newcol[x] = (unsigned char)min(r, m - 1);
+      }
+      __syncthreads();
+
+      // (e) column newcol[x] of the merge's m x m vector block V (row p: the
+      // sorted position p): e_p for a deflated position, else the normalised
+      // root vector zhat_j / (d_j - lambda_i)
+      double* const V = scr + vbase + (int64_t)lo * M;
+      if (mine) {
+        const int c = newcol[x];
+        const int ji = jof[x];
+        if (ji == 255) {
+          for (int p = 0; p < m; ++p) gst(&V[p * m + c], p == i ? 1.0 : 0.0);
+        } else {
+          const double* d = ds + lo;
+          const double lo_org = d[orgs[lo + ji]], tl = taus[lo + ji];
+          double ss = 0.0;
+          for (int q = 0; q < nk; ++q) {
+            const double u = zh[lo + q] * rcp_nr((d[q] - lo_org) - tl);
+            ss = fma(u, u, ss);
+          }
+          const double nrm = rsqrt_nr(ss);
+          for (int p = 0; p < m; ++p) {
+            const int q = jof[lo + p];
+            const double u = q == 255 ? 0.0 : zh[lo + q] * rcp_nr((d[q] - lo_org) - tl) * nrm;
+            gst(&V[p * m + c], u);
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+
+      // (f) Z[lo:hi, lo:hi] <- Z[lo:hi, perm] V, eight by eight outputs per
+      // thread; tiles of all merges of the depth are numbered in order
+      double acc[8][8];
+      int tr0 = -1, tc0 = 0, tlo = 0, thi = 0;
+      {
+        int f = tid;
+        for (int bb = 0; bb < (1 << t); ++bb) {
+          const int blo = (bb * K) >> t, bhi = ((bb + 1) * K) >> t, bmid = ((2 * bb + 1) * K) >> (t + 1);
+          if (!(blo < bmid && bmid < bhi)) continue;
+          const int nt = (bhi - blo + 7) >> 3;
+          if (f < nt * nt) {
+            tr0 = blo + 8 * (f / nt);
+            tc0 = 8 * (f % nt);
+            tlo = blo;
+            thi = bhi;
+            break;
+          }
+          f -= nt * nt;
+        }
+      }
+      if (tr0 >= 0) {
+        const int bm = thi - tlo;
+        const double* Vb = scr + vbase + (int64_t)tlo * M;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int w = 0; w < 8; ++w) acc[u][w] = 0.0;
+        int rows[8], cols[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int idx = max(m - 1 - u, l);
-          eb[u] = eo[idx];
-          db[u] = dg[idx];
+          rows[u] = min(tr0 + u, thi - 1) * ld;
+          cols[u] = min(tc0 + u, bm - 1);
         }
-        int i0 = m - 1;
-        while (i0 - 7 >= l) {
-          const double sn0 = sn, cs0 = cs, p0 = p, g0 = g, d0 = d_i1;
-          double oe[8], od[8], oc[8], os[8];
+        for (int p = 0; p < bm; ++p) {
+          const int col = perm[tlo + p];
+          double zr[8], vr[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const double f = sn * eb[u], bb = cs * eb[u];
-            const double x2 = f * f + g * g;
-            const double ir = rsqrt3(x2);
-            oe[u] = x2 * ir;
-            sn = f * ir;
-            cs = g * ir;
-            g = d_i1 - p;
-            r = (db[u] - g) * sn + 2.0 * cs * bb;
-            p = sn * r;
-            od[u] = g + p;
-            g = cs * r - bb;
-            oc[u] = cs;
-            os[u] = sn;
-            d_i1 = db[u];
-            const int idx = max(i0 - 8 - u, l);
-            eb[u] = eo[idx];
-            db[u] = dg[idx];
+            zr[u] = L[rows[u] + col];
+            vr[u] = gld(&Vb[p * bm + cols[u]]);
           }
-          if (isfinite(g) && isfinite(p)) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = i0 - u;
-              eo[i + 1] = oe[u];
-              dg[i + 1] = od[u];
-              rcs[b][i] = oc[u];
-              rss[b][i] = os[u];
-            }
-          } else {   // redo the block rotation by rotation
-            sn = sn0; cs = cs0; p = p0; g = g0; d_i1 = d0;
-            for (int u = 0; u < 8 && !split; ++u) split = !step(i0 - u, eo[i0 - u], dg[i0 - u]);
-            if (split) break;
-          }
-          i0 -= 8;
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int w = 0; w < 8; ++w) acc[u][w] = fma(zr[u], vr[w], acc[u][w]);
         }
-        // the tail: fewer than eight rotations, operands already in eb, db
-        for (int u = 0; u < 8 && !split && i0 - u >= l; ++u) split = !step(i0 - u, eb[u], db[u]);
-        if (split) {
-          eo[m] = 0.0;
-        } else {
-          dg[l] = d_i1 - p;
-          eo[l] = g;
-          eo[m] = 0.0;
-        }
-        sw_m[b] = m;
-        sw_lo[b] = lo;   // rotations m-1 .. lo were formed
-        sw_state[b] = SWEEP_ROT;
       }
-      return;
-    }
-  };
-  if (wave == 0) produce(0);
-  __syncthreads();
-  for (int b = 0;; b ^= 1) {
-    if (sw_state[b] == SWEEP_DONE) break;
-    if (wave == 0) {
-      produce(b ^ 1);
-    } else {
-      // apply sweep b: rotations m-1 .. lo to each row of Z, eight per LDS
-      // round trip; loads are clamped to lo and invalid lanes keep the carry
-      const int m = sw_m[b], lo = sw_lo[b];
-      const double* rc = rcs[b];
-      const double* rs = rss[b];
-      const int kr = tid - 64;
-      if (kr < K && lo <= m - 1) {
-        double* row = &L[kr * ld];
-        double carry = row[m];
-        for (int i = m - 1; i >= lo; i -= 8) {
-          double xv[8], cv[8], sv[8];
+      __syncthreads();
+      if (tr0 >= 0) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int iu = max(i - u, lo);
-            xv[u] = row[iu];
-            cv[u] = rc[iu];
-            sv[u] = rs[iu];
-          }
-          double o[8];
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            o[u] = sv[u] * xv[u] + cv[u] * carry;
-            const double nc = cv[u] * xv[u] - sv[u] * carry;
-            carry = i - u >= lo ? nc : carry;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) *(i - u >= lo ? &row[i - u + 1] : &row[K]) = o[u];
-        }
-        row[lo] = carry;
+          for (int w = 0; w < 8; ++w)
+            if (tr0 + u < thi && tc0 + w < thi - tlo) L[(tr0 + u) * ld + tlo + tc0 + w] = acc[u][w];
       }
+      if (mine) dg[lo + newcol[x]] = nv[x];
+      __syncthreads();
+      vbase += dc_region_doubles(K, t);
     }
+    if (run && tid < K) dg[tid] *= scale;
     __syncthreads();
   }
 
@@ -429,13 +569,13 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       const double lj = dg[j];
       if (lj > li || (lj == li && j < i)) ++pos;
     }
-    rankpos[i] = pos;
+    newcol[i] = (unsigned char)pos;
     gst(&a.lam[pos], fmax(li, 0.0));
     if (!isfinite(li)) atomicOr(&st->flags, 2u);
   }
-  if (tid == 0) {   // wave 0, lane 0: the producer's counters
-    atomicMax(&st->pad, min(max_it, 255));
-    if (noconv) atomicOr(&st->flags, 8u);
+  if (tid == 0) {   // the secular-equation counters of the merges
+    atomicMax(&st->pad, min(sh_maxit, 255));
+    if (sh_noconv) atomicOr(&st->flags, 8u);
   }
   __syncthreads();
 #pragma unroll
@@ -443,7 +583,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
       const int r = rl + 16 * i, c = cg + 16 * q;
-      if (r < K && c < K) gst(&a.Q[r * K + rankpos[c]], Z[i][q]);
+      if (r < K && c < K) gst(&a.Q[r * K + newcol[c]], Z[i][q]);
     }
 }
 

@@ -14,6 +14,29 @@ constexpr int KMAX = 128;
 // Segments of a segmented reduction (one per summand of a lazy sum).
 constexpr int MAX_SEG = 8;
 
+// Eigensolver scratch layout (eig.hip), in doubles from the node's scratch
+// pointer: the Householder reflectors (K x K) and their tau (K), then the
+// eigenvector blocks of the divide-and-conquer merges.  The tridiagonal of
+// order K is cut in halves down to single rows: at depth t block b is
+// [floor(b K / 2^t), floor((b+1) K / 2^t)), at most ceil(K / 2^t) rows, and
+// merges its two halves.  The merges of depth t write their m x m eigenvector
+// blocks into a region of K ceil(K / 2^t) + 8 doubles of their own (block
+// [lo, hi) at lo * ceil(K / 2^t)), so no address is written twice in a launch.
+__host__ __device__ inline int dc_depths(int K) {          // ceil(log2 K), 0 for K <= 1
+  int t = 0;
+  while ((1 << t) < K) ++t;
+  return t;
+}
+__host__ __device__ inline int64_t dc_region_doubles(int K, int t) {
+  return (int64_t)K * (((K - 1) >> t) + 1) + 8;
+}
+__host__ __device__ inline int64_t eig_reflector_doubles(int K) { return (int64_t)K * K + K + 64; }
+__host__ __device__ inline int64_t eig_scratch_doubles(int K) {
+  int64_t s = eig_reflector_doubles(K);
+  for (int t = 0; t < dc_depths(K); ++t) s += dc_region_doubles(K, t);
+  return s;
+}
+
 // Element types of GEMM operands / results.
 enum DType : int { F64 = 0, F32 = 1 };
 
@@ -126,7 +149,7 @@ struct SmallArgs {
   void* QmT;               // rcap x K transpose in the forward type
   int32_t* rank_dev;       // rank of this node (device)
   double* sigma_out;       // optional: 128 slots for sigma / ||A||
-  double* scratch;         // eigensolver scratch, 3 K^2 doubles
+  double* scratch;         // eigensolver scratch, eig_scratch_doubles(K)
   double* Bh;              // K x K Gramian (eigensolver input)
   struct GlobalState* st;  // state of the tensor this node belongs to (NULL: the launch's)
 };
