@@ -15,10 +15,11 @@
 //     rank-one update D + rho z z^T, z = Q^T v / sqrt(2) (rho doubled):
 //       - the eigenvalues are sorted; entries with rho |z_j| below
 //         2 u max|D| of the block, and pairs of poles closer than that after a
-//         plane rotation of their z entries, deflate (one wave per merge runs
-//         the scan, its lanes rotate the two eigenvector columns);
+//         plane rotation of their z entries, deflate (a wave per merge at
+//         the top four depths, else a thread, runs the scan and rotates the
+//         two eigenvector columns);
 //       - each remaining root of 1 + rho sum_j z_j^2 / (d_j - lambda) = 0 is
-//         found by one thread: origin at the nearer pole, a start from the
+//         found by a pair of threads: origin at the nearer pole, a start from the
 //         two nearest poles with the other terms frozen at the midpoint, then
 //         the two-pole model matching psi, psi' and phi, phi' (Bunch, Nielsen
 //         and Sorensen), bracketed by bisection;
@@ -61,23 +62,29 @@ __device__ __forceinline__ double dc_quad(double c, double b1, double b2, double
   return low ? y : -y;
 }
 
+// Sum over the two lanes of a pair (2x, 2x+1).
+__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, 1, 64); }
+
 // Root i of the secular equation 1 + rho sum_j z_j^2 / (d_j - lambda) = 0
 // for poles d[0] < ... < d[nk-1] (the root lies in (d_i, d_i+1), the last
-// one in (d_nk-1, d_nk-1 + rho |z|^2]).  Returns lambda = d[org] + tau with
-// the origin pole org and the offset tau (so d_j - lambda is formed as
+// one in (d_nk-1, d_nk-1 + rho |z|^2]), found by the two lanes of a pair, each
+// summing every other pole (par = lane parity).  Returns lambda = d[org] + tau
+// with the origin pole org and the offset tau (so d_j - lambda is formed as
 // (d_j - d_org) - tau, without cancellation).  *iters: iterations taken;
 // *conv: false if the iteration limit was reached.
-__device__ void dc_root(int i, int nk, const double* d, const double* z, double rho, int* org_out,
+__device__ void dc_root(int i, int nk, const double* d, const double* z, double rho, int par, int* org_out,
                         double* tau_out, int* iters, bool* conv) {
   int org;
   double lo_t, hi_t, tau;
   if (i < nk - 1) {
     const double di = d[i], hw = 0.5 * (d[i + 1] - di);
-    double f = 1.0;
-    for (int j = 0; j < nk; ++j) {
+    double f = 0.0;
+    #pragma unroll 4
+    for (int j = par; j < nk; j += 2) {
       const double del = (d[j] - di) - hw;
       f += rho * z[j] * z[j] * rcp_nr(del);
     }
+    f = 1.0 + pair_sum(f);
     const double wi = rho * z[i] * z[i], wi1 = rho * z[i + 1] * z[i + 1];
     const double ti = wi * rcp_nr(-hw), ti1 = wi1 * rcp_nr((d[i + 1] - di) - hw);
     if (f >= 0.0) {
@@ -90,7 +97,8 @@ __device__ void dc_root(int i, int nk, const double* d, const double* z, double 
     if (lo_t < x0 && x0 < hi_t) tau = x0;
   } else {
     double zz = 0.0;
-    for (int j = 0; j < nk; ++j) zz += z[j] * z[j];
+    for (int j = par; j < nk; j += 2) zz += z[j] * z[j];
+    zz = pair_sum(zz);
     org = nk - 1; lo_t = 0.0; hi_t = rho * zz; tau = hi_t;
   }
   const double dorg = d[org];
@@ -99,12 +107,15 @@ __device__ void dc_root(int i, int nk, const double* d, const double* z, double 
   bool ok = false;
   for (; it < 64; ++it) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, sabs = 0.0;
-    for (int j = 0; j < nk; ++j) {
+    #pragma unroll 4
+    for (int j = par; j < nk; j += 2) {
       const double inv = rcp_nr((d[j] - dorg) - tau);
       const double tj = rho * z[j] * z[j] * inv, dtj = tj * inv;
       if (j <= i) { psi += tj; dpsi += dtj; } else { phi += tj; dphi += dtj; }
       sabs += fabs(tj);
     }
+    psi = pair_sum(psi); dpsi = pair_sum(dpsi); phi = pair_sum(phi); dphi = pair_sum(dphi);
+    sabs = pair_sum(sabs);
     const double f = 1.0 + psi + phi;
     if (fabs(f) <= kUnit * (8.0 * (1.0 + sabs) + fabs(tau) * (dpsi + dphi))) { ok = true; break; }
     if (f > 0.0) hi_t = tau; else lo_t = tau;
@@ -292,10 +303,11 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
     const int T = run ? dc_depths(K) : 0;
     int64_t vbase = eig_reflector_doubles(K);
     double* const scr = a.scratch;
+    // two threads per position x of the tridiagonal (K <= 128 = NT / 2)
+    const int x = tid >> 1, h = tid & 1;
     for (int t = T - 1; t >= 0; --t) {
       const int M = ((K - 1) >> t) + 1;          // rows of the largest block at this depth
-      // the merge of position x (tid): block b of depth t
-      const int x = tid;
+      // the merge of position x: block b of depth t
       int b = 0, lo = 0, mid = 0, hi = 0;
       bool mine = false;
       if (x < K) {
@@ -312,94 +324,105 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       if (mine) {
         const double v = dg[x];
         int r = 0;
-        for (int y = lo; y < hi; ++y) {
+        for (int y = lo + h; y < hi; y += 2) {
           const double w = dg[y];
           r += (w < v || (w == v && y < x)) ? 1 : 0;
         }
+        r += __shfl_xor(r, 1, 64);
         r = min(r, m - 1);
-        const double sgn = eo[mid - 1] >= 0.0 ? 1.0 : -1.0;
-        const double zx = (x < mid ? L[(mid - 1) * ld + x] : sgn * L[mid * ld + x]) * 0.70710678118654752;
-        perm[lo + r] = (unsigned char)x;
-        ds[lo + r] = v;
-        zs[lo + r] = zx;
+        if (h == 0) {
+          const double sgn = eo[mid - 1] >= 0.0 ? 1.0 : -1.0;
+          const double zx = (x < mid ? L[(mid - 1) * ld + x] : sgn * L[mid * ld + x]) * 0.70710678118654752;
+          perm[lo + r] = (unsigned char)x;
+          ds[lo + r] = v;
+          zs[lo + r] = zx;
+        }
       }
       __syncthreads();
 
-      // (b) deflation: one wave per merge scans the sorted entries, its lanes
-      // rotate eigenvector columns; kept poles are compacted in place
-      for (int bb = wave; bb < (1 << t); bb += NT / 64) {
-        const int blo = (bb * K) >> t, bhi = ((bb + 1) * K) >> t, bmid = ((2 * bb + 1) * K) >> (t + 1);
-        if (!(blo < bmid && bmid < bhi)) continue;
-        const int bm = bhi - blo;
-        const double brho = 2.0 * fabs(eo[bmid - 1]);
-        const double tol = 2.0 * kUnit * fmax(fabs(ds[blo]), fabs(ds[bhi - 1]));
-        int nk = 0, pk = -1;
-        for (int p = 0; p < bm; ++p) {
-          const int P = blo + p;
-          const double zp = zs[P], dp = ds[P];
-          if (brho * fabs(zp) <= tol) {
-            if (lane == 0) { nv[P] = dp; jof[P] = 255; }
-            continue;
+      // (b) deflation: the sorted entries of a merge are scanned in order by
+      // a wave (at most four merges at this depth; its lanes rotate the rows
+      // of two eigenvector columns) or by a single thread; kept poles are
+      // compacted in place
+      {
+        const bool wide = (1 << t) <= NT / 64;
+        const int g = wide ? wave : tid, gl = wide ? lane : 0, gs = wide ? 64 : 1;
+        for (int bb = g; bb < (1 << t); bb += wide ? NT / 64 : NT) {
+          const int blo = (bb * K) >> t, bhi = ((bb + 1) * K) >> t, bmid = ((2 * bb + 1) * K) >> (t + 1);
+          if (!(blo < bmid && bmid < bhi)) continue;
+          const int bm = bhi - blo;
+          const double brho = 2.0 * fabs(eo[bmid - 1]);
+          const double tol = 2.0 * kUnit * fmax(fabs(ds[blo]), fabs(ds[bhi - 1]));
+          int nk = 0, pk = -1;
+          for (int p = 0; p < bm; ++p) {
+            const int P = blo + p;
+            const double zp = zs[P], dp = ds[P];
+            if (brho * fabs(zp) <= tol) {
+              if (gl == 0) { nv[P] = dp; jof[P] = 255; }
+              continue;
+            }
+            if (pk >= 0) {
+              const int PK = blo + pk;
+              const double zq = zs[PK], dq = ds[PK];
+              const double tau = sqrt(fma(zq, zq, zp * zp));
+              const double c = zp / tau, sn = -zq / tau;
+              if (fabs((dp - dq) * c * sn) <= tol) {
+                // rotate so that z_pk = 0: position pk deflates
+                const int ca = perm[PK], cb = perm[P];
+                for (int r = blo + gl; r < bhi; r += gs) {
+                  const double u = L[r * ld + ca], w = L[r * ld + cb];
+                  L[r * ld + ca] = c * u + sn * w;
+                  L[r * ld + cb] = c * w - sn * u;
+                }
+                if (gl == 0) {
+                  zs[P] = tau;
+                  nv[PK] = dq * c * c + dp * sn * sn;
+                  jof[PK] = 255;
+                  ds[P] = dq * sn * sn + dp * c * c;
+                }
+              } else {
+                if (gl == 0) {
+                  kidx[blo + nk] = (unsigned char)pk;
+                  jof[PK] = (unsigned char)nk;
+                  ds[blo + nk] = dq;
+                  zs[blo + nk] = zq;
+                }
+                ++nk;
+              }
+            }
+            pk = p;
           }
           if (pk >= 0) {
             const int PK = blo + pk;
-            const double zq = zs[PK], dq = ds[PK];
-            const double tau = sqrt(fma(zq, zq, zp * zp));
-            const double c = zp / tau, sn = -zq / tau;
-            if (fabs((dp - dq) * c * sn) <= tol) {
-              // rotate so that z_pk = 0: position pk deflates
-              const int ca = perm[PK], cb = perm[P];
-              for (int r = blo + lane; r < bhi; r += 64) {
-                const double u = L[r * ld + ca], w = L[r * ld + cb];
-                L[r * ld + ca] = c * u + sn * w;
-                L[r * ld + cb] = c * w - sn * u;
-              }
-              if (lane == 0) {
-                zs[P] = tau;
-                nv[PK] = dq * c * c + dp * sn * sn;
-                jof[PK] = 255;
-                ds[P] = dq * sn * sn + dp * c * c;
-              }
-            } else {
-              if (lane == 0) {
-                kidx[blo + nk] = (unsigned char)pk;
-                jof[PK] = (unsigned char)nk;
-                ds[blo + nk] = dq;
-                zs[blo + nk] = zq;
-              }
-              ++nk;
+            const double dq = ds[PK], zq = zs[PK];
+            if (gl == 0) {
+              kidx[blo + nk] = (unsigned char)pk;
+              jof[PK] = (unsigned char)nk;
+              ds[blo + nk] = dq;
+              zs[blo + nk] = zq;
             }
+            ++nk;
           }
-          pk = p;
+          if (gl == 0) kcnt[bb] = (unsigned char)nk;
         }
-        if (pk >= 0) {
-          const int PK = blo + pk;
-          const double dq = ds[PK], zq = zs[PK];
-          if (lane == 0) {
-            kidx[blo + nk] = (unsigned char)pk;
-            jof[PK] = (unsigned char)nk;
-            ds[blo + nk] = dq;
-            zs[blo + nk] = zq;
-          }
-          ++nk;
-        }
-        if (lane == 0) kcnt[bb] = (unsigned char)nk;
       }
       __syncthreads();
 
-      // (c) one thread per root of the secular equation
+      // (c) two threads per root of the secular equation
       const int nk = mine ? kcnt[b] : 0;
       const int i = x - lo;
       if (mine && i < nk) {
         int org, its;
         double tau;
         bool conv;
-        dc_root(i, nk, ds + lo, zs + lo, rho, &org, &tau, &its, &conv);
-        orgs[x] = (unsigned char)org;
-        taus[x] = tau;
-        nv[lo + kidx[x]] = ds[lo + org] + tau;
-        atomicMax(&sh_maxit, its);
-        if (!conv) sh_noconv = 1;
+        dc_root(i, nk, ds + lo, zs + lo, rho, h, &org, &tau, &its, &conv);
+        if (h == 0) {
+          orgs[x] = (unsigned char)org;
+          taus[x] = tau;
+          nv[lo + kidx[x]] = ds[lo + org] + tau;
+          atomicMax(&sh_maxit, its);
+          if (!conv) sh_noconv = 1;
+        }
       }
       __syncthreads();
 
@@ -409,43 +432,48 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
         const double* d = ds + lo;
         if (i < nk) {
           const double dj = d[i];
-          double w = (taus[x] - (dj - d[orgs[x]])) / rho;   // (lambda_j - d_j) / rho
-          for (int q = 0; q < nk; ++q) {
+          double w = h == 0 ? (taus[x] - (dj - d[orgs[x]])) / rho : 1.0;   // (lambda_j - d_j) / rho
+          #pragma unroll 4
+          for (int q = h; q < nk; q += 2) {
             if (q == i) continue;
             const double lq = (d[orgs[lo + q]] - dj) + taus[lo + q];   // lambda_q - d_j
             w *= lq * rcp_nr(d[q] - dj);
           }
-          zh[x] = copysign(sqrt(fmax(w, 0.0)), zs[x]);
+          w *= __shfl_xor(w, 1, 64);
+          if (h == 0) zh[x] = copysign(sqrt(fmax(w, 0.0)), zs[x]);
         }
         const double v = nv[x];
         int r = 0;
-        for (int y = lo; y < hi; ++y) {
+        for (int y = lo + h; y < hi; y += 2) {
           const double u = nv[y];
           r += (u < v || (u == v && y < x)) ? 1 : 0;
         }
-        newcol[x] = (unsigned char)min(r, m - 1);
+        r += __shfl_xor(r, 1, 64);
+        if (h == 0) newcol[x] = (unsigned char)min(r, m - 1);
       }
       __syncthreads();
 
       // (e) column newcol[x] of the merge's m x m vector block V (row p: the
       // sorted position p): e_p for a deflated position, else the normalised
-      // root vector zhat_j / (d_j - lambda_i)
+      // root vector zhat_j / (d_j - lambda_i); the two threads of x take
+      // alternate rows
       double* const V = scr + vbase + (int64_t)lo * M;
       if (mine) {
         const int c = newcol[x];
         const int ji = jof[x];
         if (ji == 255) {
-          for (int p = 0; p < m; ++p) gst(&V[p * m + c], p == i ? 1.0 : 0.0);
+          for (int p = h; p < m; p += 2) gst(&V[p * m + c], p == i ? 1.0 : 0.0);
         } else {
           const double* d = ds + lo;
           const double lo_org = d[orgs[lo + ji]], tl = taus[lo + ji];
           double ss = 0.0;
-          for (int q = 0; q < nk; ++q) {
+          #pragma unroll 4
+          for (int q = h; q < nk; q += 2) {
             const double u = zh[lo + q] * rcp_nr((d[q] - lo_org) - tl);
             ss = fma(u, u, ss);
           }
-          const double nrm = rsqrt_nr(ss);
-          for (int p = 0; p < m; ++p) {
+          const double nrm = rsqrt_nr(pair_sum(ss));
+          for (int p = h; p < m; p += 2) {
             const int q = jof[lo + p];
             const double u = q == 255 ? 0.0 : zh[lo + q] * rcp_nr((d[q] - lo_org) - tl) * nrm;
             gst(&V[p * m + c], u);
@@ -456,7 +484,8 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       __syncthreads();
 
       // (f) Z[lo:hi, lo:hi] <- Z[lo:hi, perm] V, eight by eight outputs per
-      // thread; tiles of all merges of the depth are numbered in order
+      // thread; tiles of all merges of the depth are numbered in order (at
+      // most ceil(K/8)^2 <= NT of them for K <= 128)
       double acc[8][8];
       int tr0 = -1, tc0 = 0, tlo = 0, thi = 0;
       {
@@ -488,13 +517,29 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           rows[u] = min(tr0 + u, thi - 1) * ld;
           cols[u] = min(tc0 + u, bm - 1);
         }
+        // the operands of product p + 1 are loaded before the products of p
+        double zn[8], vn[8];
+        {
+          const int col = perm[tlo];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            zn[u] = L[rows[u] + col];
+            vn[u] = gld(&Vb[cols[u]]);
+          }
+        }
         for (int p = 0; p < bm; ++p) {
-          const int col = perm[tlo + p];
           double zr[8], vr[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            zr[u] = L[rows[u] + col];
-            vr[u] = gld(&Vb[p * bm + cols[u]]);
+            zr[u] = zn[u];
+            vr[u] = vn[u];
+          }
+          const int pn = min(p + 1, bm - 1);
+          const int col = perm[tlo + pn];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            zn[u] = L[rows[u] + col];
+            vn[u] = gld(&Vb[pn * bm + cols[u]]);
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
@@ -510,7 +555,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           for (int w = 0; w < 8; ++w)
             if (tr0 + u < thi && tc0 + w < thi - tlo) L[(tr0 + u) * ld + tlo + tc0 + w] = acc[u][w];
       }
-      if (mine) dg[lo + newcol[x]] = nv[x];
+      if (mine && h == 0) dg[lo + newcol[x]] = nv[x];
       __syncthreads();
       vbase += dc_region_doubles(K, t);
     }
