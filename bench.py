@@ -16,7 +16,9 @@ region (HIP events around every launch, on the stream it runs on) and
 `roofline_mfma` the matrix-core kernel with the largest share; `traffic` is
 the committed rocprofv3 counter figure while the kernel sources match it.
 `cpu_baseline` times the float64 NumPy oracle on one sum-truncation of the
-same workload on the host cores.
+same workload on the host cores.  `large_single` times the large single
+workload (d = 128, n = 1e5, k = 64 per summand, truncated to rank 64) and
+ht_entries of its result at 1e6 random multi-indices.
 """
 import argparse
 import json
@@ -115,6 +117,61 @@ def measured_traffic(kernel):
     return rows.get(kernel)
 
 
+def device_tensor(H, torch, d, n, k, spectrum, gen):
+    """One HT tensor of the large single workload, drawn on the device: float32
+    N(0,1) leaf frames, transfer tensors with M_1(B_t) = P diag(g) W^T (P, W
+    orthonormal from QR of N(0,1) matrices), float64 root of the same form."""
+    tr = H.ht_tree(d)
+    nn = 2 * d - 1
+    g = torch.tensor(spectrum, dtype=torch.float64, device="cuda")
+
+    def orth(rows, cols):
+        q, _ = torch.linalg.qr(torch.randn(rows, cols, dtype=torch.float64, device="cuda", generator=gen))
+        return q
+
+    leaves, transfer, ranks = [None] * d, [None] * nn, [1] * nn
+    for t in range(nn):
+        if int(tr["son1"][t]) < 0:
+            leaves[int(tr["lo"][t])] = torch.randn(k, n, dtype=torch.float32, device="cuda", generator=gen)
+            ranks[t] = k
+        elif t == 0:
+            transfer[t] = (orth(k, k) * g[None, :]) @ orth(k, k).T
+        else:
+            transfer[t] = ((orth(k, k) * g[None, :]) @ orth(k * k, k).T).reshape(k, k, k).float()
+            ranks[t] = k
+    return H.DeviceHT(d, [n] * d, ranks, leaves, transfer, 0)
+
+
+def large_single(H, torch, steps=3):
+    """The large single workload: d=128, n=1e5, k=64 per summand, spectra
+    10^(-i/16), the sum truncated to rank 64 (mixed path), then ht_entries of
+    the result at 1e6 random multi-indices."""
+    d, n, k, m = 128, 100000, 64, 1000000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    spec = [10.0 ** (-i / 16.0) for i in range(k)]
+    log("bench: large single workload d=128 n=1e5 k=64+64 -> 64 (inputs drawn on the device)")
+    A, C = device_tensor(H, torch, d, n, k, spec, gen), device_tensor(H, torch, d, n, k, spec, gen)
+    tr = H.Truncator([A, C], [1.0, 1.0], mode=H.HT_RANK_FIXED, ranks=[k] * (2 * d - 1), precision=H.HT_PREC_MIXED)
+    res = tr()
+    t_trunc = timed(tr, steps, torch)
+    log(f"bench: large single {t_trunc * 1e3:.2f} ms per sum-truncation")
+    idx = torch.randint(0, n, (m, d), dtype=torch.int32, device="cuda", generator=gen)
+    H.ht_entries(res.out, idx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.ht_entries(res.out, idx)
+    torch.cuda.synchronize()
+    t_ent = time.perf_counter() - t0
+    log(f"bench: large single ht_entries {m} indices in {t_ent * 1e3:.1f} ms")
+    out = dict(workload="HT sum truncation d=128 n=100000 k=64+64 -> 64 (mixed precision), then entries at 1e6 "
+                        "random multi-indices", ms_per_step=t_trunc * 1e3, value=1.0 / t_trunc,
+               unit="sum-truncations/s", steps=steps, entries_m=m, entries_ms=t_ent * 1e3, entries_per_s=m / t_ent)
+    del A, C, tr, res, idx
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-large", action="store_true", help="skip the large single workload (d=128, n=1e5)")
     ap.add_argument("--breakdown", action="store_true", help="print the per-step profile to stderr")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the benchmark, run three plain device copies of MIB MiB (a known "
@@ -286,6 +344,7 @@ def main():
         "roofline": roof,
         "roofline_mfma": roof_mfma,
     }
+    out["large_single"] = None if args.no_large else large_single(H, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline (one sum-truncation)")
         out["cpu_baseline"] = cpu_baseline(cfg)
