@@ -247,6 +247,34 @@ ht_status ht_truncate_batched(ht_context* ctx, int32_t count, const ht_desc* X, 
                               int32_t* const* out_ranks, int64_t* out_log2_scale, uint32_t* flags,
                               double* const* out_sigma, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- inner product and norm
+ * Inner product <X, Y> of two HT tensors on one tree (Section 3.2):
+ * Definition (phi) bottom-up, Phi_mu = U_mu^T V_mu at the leaves, eq. (defphi)
+ * Phi_t = M_1(B_t) (Phi_s1 (x) Phi_s2) M_1(F_t)^T at inner nodes (B of X, F
+ * of Y) and <X, Y> = Phi_D at the root (Lemma (phi)).  X and Y must share d
+ * and n; ranks and dtypes may differ.  The result is *out_val * 2^(*out_log2)
+ * with 0.5 <= |*out_val| < 1, or 0 (out_val: DEVICE double, out_log2: DEVICE
+ * int64, both required): every Phi_t is divided by a power of two on the way
+ * up, so no range is exceeded.  Computed in float64.  flags: DEVICE uint32 or
+ * NULL (bit 1: a non-finite value).  Workspace: ht_inner_workspace() bytes,
+ * 256-byte aligned.  Errors: HT_EINVAL, HT_ESHAPE, HT_EWORKSPACE,
+ * HT_EUNSUPPORTED (ranks above 128). */
+ht_status ht_inner_workspace(ht_context* ctx, const ht_desc* X, const ht_desc* Y, size_t* bytes);
+ht_status ht_inner(ht_context* ctx, const ht_desc* X, const ht_desc* Y, double* out_val, int64_t* out_log2,
+                   uint32_t* flags, void* ws, size_t ws_bytes, void* stream);
+
+/* Norm of the lazy sum S = sum_c coef[c] X[c] (n_in in [1, 8] summands with
+ * equal d and n, coef NULL: all 1): S is orthogonalised bottom-up (Section
+ * 3.4, the R factors only, float64) and ||S|| is the Frobenius norm of the
+ * orthogonal root matrix.  With X = {A, B} and coef = {1, -1} this is the
+ * difference norm ||A - B||, which does not suffer the cancellation of
+ * <A,A> - 2<A,B> + <B,B>.  Result *out_val * 2^(*out_log2) as for ht_inner.
+ * flags: DEVICE uint32 or NULL, as for ht_truncate.  Workspace:
+ * ht_norm_workspace() bytes, 256-byte aligned.  Errors: as ht_truncate. */
+ht_status ht_norm_workspace(ht_context* ctx, const ht_desc* X, int32_t n_in, size_t* bytes);
+ht_status ht_norm(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in, double* out_val,
+                  int64_t* out_log2, uint32_t* flags, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- entries
  * A[i_1..i_d] for m multi-indices (Section 3.1): leaves pick row i_mu, inner
  * nodes apply eq. (transfermult), the root the root formula; evaluated level

@@ -29,6 +29,8 @@ ht_status ht_debug_plan_key_repeats(const ht_desc* X, int32_t n_in, const ht_tru
 ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision);
 ht_status ht_debug_validate_gramians(const ht_desc* X);
 ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m);
+ht_status ht_debug_validate_inner(const ht_desc* X, const ht_desc* Y);
+ht_status ht_debug_validate_norm(const ht_desc* X, int32_t n_in);
 #ifdef __cplusplus
 }
 #endif

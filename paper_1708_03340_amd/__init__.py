@@ -29,6 +29,7 @@ EXPORTS = [
     "ht_tree", "ht_add", "ht_orthogonalize_workspace", "ht_orthogonalize", "ht_gramians_workspace",
     "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_truncate_batched_workspace",
     "ht_truncate_batched", "ht_entries_workspace", "ht_entries", "ht_truncate_noalloc",
+    "ht_inner_workspace", "ht_inner", "ht_norm_workspace", "ht_norm",
     "ht_profile_enable", "ht_profile_read", "ht_profile_reset",
 ]
 
@@ -103,6 +104,10 @@ def lib(path: Optional[str] = None):
                               VP, VP, ctypes.c_size_t, VP]
     L.ht_truncate_noalloc.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, P(HtTruncOpts), P(HtDesc), VP,
                                       VP, VP, VP, VP]
+    L.ht_inner_workspace.argtypes = [VP, P(HtDesc), P(HtDesc), P(ctypes.c_size_t)]
+    L.ht_inner.argtypes = [VP, P(HtDesc), P(HtDesc), VP, VP, VP, VP, ctypes.c_size_t, VP]
+    L.ht_norm_workspace.argtypes = [VP, P(HtDesc), I32, P(ctypes.c_size_t)]
+    L.ht_norm.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, VP, VP, VP, VP, ctypes.c_size_t, VP]
     L.ht_truncate_batched_workspace.argtypes = [VP, I32, P(HtDesc), P(I32), P(HtTruncOpts), P(ctypes.c_size_t)]
     L.ht_truncate_batched.argtypes = [VP, I32, P(HtDesc), P(I32), P(ctypes.c_double), P(HtTruncOpts), P(HtDesc),
                                       P(VP), VP, VP, P(VP), VP, ctypes.c_size_t, VP]
@@ -545,6 +550,65 @@ def ht_entries(X: DeviceHT, idx, ctx=None, stream=None):
     _check(lib().ht_entries(ctx.h, ctypes.byref(d), m, _ptr(idx), _ptr(out), _ptr(ws), ws.numel(),
                             _stream_ptr(stream)))
     return out
+
+
+class Scaled:
+    """A device result m * 2^e (m: float64 tensor, e: int64 tensor, one element each)."""
+
+    def __init__(self, m, e, flags=None):
+        self.m, self.e, self.flags_dev = m, e, flags
+
+    def mantissa_exponent(self):
+        return float(self.m.item()), int(self.e.item())
+
+    def value(self) -> float:
+        """As a Python float (inf or 0 outside the float64 range)."""
+        m, e = self.mantissa_exponent()
+        return float(np.ldexp(m, int(np.clip(e, -20000, 20000))))
+
+    def log2_abs(self) -> float:
+        m, e = self.mantissa_exponent()
+        return float(np.log2(abs(m)) + e) if m != 0.0 else float("-inf")
+
+
+def ht_inner(X: DeviceHT, Y: DeviceHT, ctx=None, stream=None) -> Scaled:
+    """<X, Y> by Definition (phi) / Lemma (phi), enqueued on the current stream."""
+    import torch
+    ctx = ctx or ht_create_context()
+    dx, dy = X.desc(), Y.desc()
+    need = ctypes.c_size_t(0)
+    _check(lib().ht_inner_workspace(ctx.h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(need)))
+    ws = _ws(need.value)
+    m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    e = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(lib().ht_inner(ctx.h, ctypes.byref(dx), ctypes.byref(dy), _ptr(m), _ptr(e), _ptr(flags), _ptr(ws),
+                          ws.numel(), _stream_ptr(stream)))
+    res = Scaled(m, e, flags)
+    res._ws = ws
+    return res
+
+
+def ht_norm(Xs, coef=None, ctx=None, stream=None) -> Scaled:
+    """||sum_c coef[c] Xs[c]|| through the orthogonalised lazy sum (Section 3.4);
+    ht_norm([A, B], [1, -1]) is the difference norm."""
+    import torch
+    ctx = ctx or ht_create_context()
+    if isinstance(Xs, DeviceHT):
+        Xs = [Xs]
+    arr, keep = _descs(Xs)
+    cf = (ctypes.c_double * len(Xs))(*([1.0] * len(Xs) if coef is None else list(coef)))
+    need = ctypes.c_size_t(0)
+    _check(lib().ht_norm_workspace(ctx.h, arr, len(Xs), ctypes.byref(need)))
+    ws = _ws(need.value)
+    m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    e = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(lib().ht_norm(ctx.h, arr, cf, len(Xs), _ptr(m), _ptr(e), _ptr(flags), _ptr(ws), ws.numel(),
+                         _stream_ptr(stream)))
+    res = Scaled(m, e, flags)
+    res._ws = ws
+    return res
 
 
 # ---------------------------------------------------------------- profiling

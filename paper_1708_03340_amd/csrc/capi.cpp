@@ -73,7 +73,7 @@ namespace {
 
 enum OpKind : int {
   OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
-  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH,
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_PHI,
   OP_FORK,   // the library's second stream waits for the caller's stream here
   OP_JOIN    // the caller's stream waits for everything on the second stream
 };
@@ -385,6 +385,23 @@ void add_state(Plan& P, int kind, const std::vector<StateRec>& r) {
 }
 
 // Fork to or join from the second stream.
+void add_phi(Plan& P, const std::vector<PhiRec>& r) {
+  if (r.empty()) return;
+  Op op;
+  op.kind = OP_PHI;
+  op.count = (int)r.size();
+  op.toff = put(P, r);
+  op.label = g_label;
+  op.stream = g_stream;
+  P.ops.push_back(op);
+}
+
+PhiRec blank_phi() {
+  PhiRec r;
+  std::memset(&r, 0, sizeof(r));
+  return r;
+}
+
 void add_sync(Plan& P, int kind) {
   Op op; op.kind = kind; op.label = kind == OP_FORK ? "fork" : "join";
   P.ops.push_back(op);
@@ -827,6 +844,9 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
       case OP_COPY:
         e = launch_copy3(reinterpret_cast<const CopyRec*>(tb + op.toff), op.count, op.c[0], stream);
         break;
+      case OP_PHI:
+        e = launch_phi_scale(reinterpret_cast<const PhiRec*>(tb + op.toff), op.count, stream);
+        break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     if (prof && ev0 && ev1) {
@@ -878,6 +898,7 @@ std::string kernel_name(const Op& op) {
     case OP_EGATHER: return "gather_kernel";
     case OP_ENORM: return "normalize_kernel";
     case OP_EFINISH: return "finish_kernel";
+    case OP_PHI: return "phi_scale_kernel";
     case OP_FORK: return "fork";
     case OP_JOIN: return "join";
   }
@@ -1010,9 +1031,10 @@ struct OrthOut {
 // is formed on the second stream while the next level's first Cholesky step
 // (a few workgroups) leaves the chip idle; the caller's stream waits for it
 // at the end.
+// form_qo: false when only the R factors and the root are wanted (a norm).
 void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, OrthOut& O,
                const std::vector<int>& rcap, bool need_proj_bufs, const ht_desc* out,
-               const ht_desc* inplace, bool overlap = false) {
+               const ht_desc* inplace, bool overlap = false, bool form_qo = true) {
   const int nn = tr.nn, d = tr.d;
   // Precision policy.  The first CholeskyQR2 sweeps (leaf frames and M_{2,3}
   // of every transfer tensor) run on the FP32 matrix cores in the mixed path:
@@ -1073,7 +1095,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
         tmpn += (size_t)S.X[c]->rank[t] * S.X[c]->rank[tr.son1[t]] * K2;
       b.Tmp = A.take(tmpn * tsz);
       b.Y = (double*)A.take(vol * 8);
-      b.Qo = A.take(vol * tsz);
+      if (form_qo) b.Qo = A.take(vol * tsz);
       if (need_proj_bufs) {
         b.C = (double*)A.take(vol * 8);
       }
@@ -1317,7 +1339,9 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       P.ops.back().p0 = O.st;
     }
     g_label = "inner_orth_factor";
-    if (overlap)
+    if (!form_qo)
+      ;
+    else if (overlap)
       pending_dq = dq;   // formed during the next level
     else
       add_gemm(P, dq, F64, T, inplace ? inplace->transfer_dtype : T, MATH_F64, GEMM_STORE, false, false);
@@ -2220,6 +2244,271 @@ ht_status ht_gramians(ht_context* ctx, const ht_desc* X, double* const* bhat, do
   return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
 }
 
+// ------------------------------------------------------------------ inner product (Section 3.2)
+// A descriptor whose NULL data arrays are replaced by placeholder addresses
+// (workspace queries plan with fake pointers and never dereference them).
+struct Placeholder {
+  ht_desc d{};
+  std::vector<void*> leaves, trans;
+  std::vector<int64_t> lds;
+  explicit Placeholder(const ht_desc* X) : d(*X) {
+    leaves.assign(X->d, (void*)256);
+    trans.assign(2 * X->d - 1, (void*)256);
+    lds.assign(X->n, X->n + X->d);
+    if (!X->leaf) d.leaf = leaves.data();
+    if (!X->transfer) d.transfer = trans.data();
+    if (!X->leaf_ld) d.leaf_ld = lds.data();
+  }
+};
+
+// <X, Y> by Definition (phi), bottom-up one tree level per launch:
+//   leaves        Phi_mu = U_mu^T V_mu                      (split-K products)
+//   inner nodes   eq. (defphi): T1 = B_t x_2 Phi_s1^T, T2 = T1 x_3 Phi_s2^T,
+//                 Phi_t = M_1(T2) M_1(F_t)^T
+//   root          Phi_D = sum_{b,c} B_D[b,c] (Phi_t1 F_D Phi_t2^T)[b,c]
+// (B: transfer tensors of X, F: of Y).  After each level every Phi_t is
+// divided by a power of two and the exponents are summed up the tree, so
+// the result is out_val * 2^out_log2 with 0.5 <= |out_val| < 1 (or 0).
+static ht_status build_inner(const ht_desc* X, const ht_desc* Y, double* out_val, int64_t* out_log2,
+                             uint32_t* flags, void* ws, Plan& P, size_t* need) {
+  ht_status st;
+  if ((st = check_desc(X, "X")) || (st = check_desc(Y, "Y"))) return st;
+  if (X->d != Y->d) return fail(HT_ESHAPE, "X and Y must share d");
+  const int d = X->d;
+  for (int mu = 0; mu < d; ++mu)
+    if (X->n[mu] != Y->n[mu]) return fail(HT_ESHAPE, "X and Y must share n");
+  Tree tr(d);
+  const int nn = tr.nn;
+  for (int t = 1; t < nn; ++t)
+    if (X->rank[t] > KMAX || Y->rank[t] > KMAX) return fail(HT_EUNSUPPORTED, "ranks above 128");
+  Arena A(ws);
+  // zero region: the split-K targets Phi_t (k^X_t x k^Y_t) and the root value
+  std::vector<double*> phi(nn, nullptr);
+  const size_t z0 = align256(A.off);
+  A.off = z0;
+  for (int t = 1; t < nn; ++t) phi[t] = (double*)A.take((size_t)X->rank[t] * Y->rank[t] * 8);
+  phi[0] = (double*)A.take(8);
+  const size_t zbytes = A.off - z0;
+  void* zptr = A.base ? A.base + z0 : nullptr;
+  reg(zptr, zbytes, "zero region");
+  std::vector<long long*> E(nn, nullptr);
+  for (int t = 0; t < nn; ++t) E[t] = (long long*)A.take(8);
+  // per-level temporaries, reused level after level (one stream)
+  size_t t1max = 0, t2max = 0;
+  const int H = tr.height[0];
+  for (int h = 1; h < H; ++h) {
+    size_t a = 0, b = 0;
+    for (int t = 1; t < nn; ++t) {
+      if (tr.is_leaf(t) || tr.height[t] != h) continue;
+      const int s1 = tr.son1[t], s2 = tr.son2[t];
+      a += (size_t)X->rank[t] * Y->rank[s1] * X->rank[s2];
+      b += (size_t)X->rank[t] * Y->rank[s1] * Y->rank[s2];
+    }
+    t1max = std::max(t1max, a);
+    t2max = std::max(t2max, b);
+  }
+  double* T1 = (double*)A.take(std::max<size_t>(t1max, 1) * 8);
+  double* T2 = (double*)A.take(std::max<size_t>(t2max, 1) * 8);
+  const int r1 = tr.son1[0], r2 = tr.son2[0];
+  double* W1 = (double*)A.take((size_t)X->rank[r1] * Y->rank[r2] * 8);
+  double* W2 = (double*)A.take((size_t)X->rank[r1] * X->rank[r2] * 8);
+  if (need) *need = align256(A.off) + 256;
+  if (!ws) return HT_OK;
+
+  const int fX = X->frame_dtype, fY = Y->frame_dtype, tX = X->transfer_dtype, tY = Y->transfer_dtype;
+  g_label = "inner_setup";
+  add_fill(P, zptr, zbytes);
+  // leaves
+  g_label = "inner_leaf";
+  {
+    std::vector<GemmDesc> dl;
+    std::vector<PhiRec> pr;
+    for (int mu = 0; mu < d; ++mu) {
+      const int t = tr.leaf_node[mu];
+      GemmDesc g = blank_desc();
+      g.A = X->leaf[mu]; g.sAm = X->leaf_ld[mu]; g.sAk = 1;
+      g.B = Y->leaf[mu]; g.sBk = 1; g.sBn = Y->leaf_ld[mu];
+      g.C = phi[t]; g.sCm = Y->rank[t]; g.sCn = 1;
+      g.M = X->rank[t]; g.N = Y->rank[t]; g.K = (int)X->n[mu];
+      dl.push_back(g);
+      PhiRec r = blank_phi();
+      r.P = phi[t]; r.n = (int64_t)X->rank[t] * Y->rank[t]; r.E = E[t]; r.flags = flags;
+      pr.push_back(r);
+    }
+    add_gemm(P, dl, fX, fY, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    add_phi(P, pr);
+  }
+  // inner nodes by height
+  for (int h = 1; h < H; ++h) {
+    std::vector<GemmDesc> d1, d2, d3;
+    std::vector<PhiRec> pr;
+    size_t o1 = 0, o2 = 0;
+    for (int t = 1; t < nn; ++t) {
+      if (tr.is_leaf(t) || tr.height[t] != h) continue;
+      const int s1 = tr.son1[t], s2 = tr.son2[t];
+      const int a = X->rank[t], b = X->rank[s1], c = X->rank[s2];
+      const int f = Y->rank[t], dd = Y->rank[s1], e = Y->rank[s2];
+      double* t1 = T1 + o1;
+      double* t2 = T2 + o2;
+      o1 += (size_t)a * dd * c;
+      o2 += (size_t)a * dd * e;
+      // T1[a][d][c] = sum_b Phi_s1[b][d] B[a][b][c]   (one product per a)
+      GemmDesc g = blank_desc();
+      g.A = phi[s1]; g.sAm = 1; g.sAk = dd;
+      g.B = X->transfer[t]; g.sBk = c; g.sBn = 1; g.sBb = (int64_t)b * c;
+      g.C = t1; g.sCm = c; g.sCn = 1; g.sCb = (int64_t)dd * c;
+      g.M = dd; g.N = c; g.K = b; g.nbatch = a;
+      d1.push_back(g);
+      // T2[(a,d)][e] = sum_c T1[(a,d)][c] Phi_s2[c][e]
+      GemmDesc q = blank_desc();
+      q.A = t1; q.sAm = c; q.sAk = 1;
+      q.B = phi[s2]; q.sBk = e; q.sBn = 1;
+      q.C = t2; q.sCm = e; q.sCn = 1;
+      q.M = a * dd; q.N = e; q.K = c;
+      d2.push_back(q);
+      // Phi_t[a][f] = sum_{(d,e)} T2[a][(d,e)] F[f][(d,e)]
+      GemmDesc r = blank_desc();
+      r.A = t2; r.sAm = (int64_t)dd * e; r.sAk = 1;
+      r.B = Y->transfer[t]; r.sBk = 1; r.sBn = (int64_t)dd * e;
+      r.C = phi[t]; r.sCm = f; r.sCn = 1;
+      r.M = a; r.N = f; r.K = dd * e;
+      d3.push_back(r);
+      PhiRec pz = blank_phi();
+      pz.P = phi[t]; pz.n = (int64_t)a * f; pz.E = E[t]; pz.E1 = E[s1]; pz.E2 = E[s2]; pz.flags = flags;
+      pr.push_back(pz);
+    }
+    if (pr.empty()) continue;
+    g_label = "inner_mode2";
+    add_gemm(P, d1, F64, tX, F64, MATH_F64, GEMM_STORE, false, false);
+    g_label = "inner_mode3";
+    add_gemm(P, d2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    g_label = "inner_contract";
+    add_gemm(P, d3, F64, tY, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    add_phi(P, pr);
+  }
+  // root: W1 = Phi_t1 F_D, W2 = W1 Phi_t2^T, Phi_D = <B_D, W2>
+  g_label = "inner_root";
+  {
+    const int b = X->rank[r1], c = X->rank[r2], dd = Y->rank[r1], e = Y->rank[r2];
+    GemmDesc g = blank_desc();
+    g.A = phi[r1]; g.sAm = dd; g.sAk = 1;
+    g.B = Y->transfer[0]; g.sBk = e; g.sBn = 1;
+    g.C = W1; g.sCm = e; g.sCn = 1;
+    g.M = b; g.N = e; g.K = dd;
+    add_gemm(P, {g}, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
+    GemmDesc q = blank_desc();
+    q.A = W1; q.sAm = e; q.sAk = 1;
+    q.B = phi[r2]; q.sBk = 1; q.sBn = e;
+    q.C = W2; q.sCm = c; q.sCn = 1;
+    q.M = b; q.N = c; q.K = e;
+    add_gemm(P, {q}, F64, F64, F64, MATH_F64, GEMM_STORE, true, true);
+    GemmDesc r = blank_desc();
+    r.A = X->transfer[0]; r.sAm = (int64_t)b * c; r.sAk = 1;
+    r.B = W2; r.sBk = 1; r.sBn = (int64_t)b * c;
+    r.C = phi[0]; r.sCm = 1; r.sCn = 1;
+    r.M = 1; r.N = 1; r.K = b * c;
+    add_gemm(P, {r}, F64, F64, F64, MATH_F64, GEMM_ATOMIC, true, true);
+    PhiRec pz = blank_phi();
+    pz.P = phi[0]; pz.n = 1; pz.E = E[0]; pz.E1 = E[r1]; pz.E2 = E[r2];
+    pz.out_val = out_val; pz.out_log2 = reinterpret_cast<long long*>(out_log2);
+    pz.add = X->log2_scale + Y->log2_scale; pz.flags = flags; pz.mode = 1;
+    add_phi(P, {pz});
+  }
+  return HT_OK;
+}
+
+// ||sum_c coef_c X_c|| as out_val * 2^out_log2: the lazy sum is orthogonalised
+// bottom-up (Section 3.4, the R factors only) and the norm of an orthogonal
+// HT tensor is the Frobenius norm of its root matrix.  With X_1 - X_2 this is
+// the difference norm, free of the cancellation of <X,X> - 2<X,Y> + <Y,Y>.
+static ht_status build_norm(const ht_desc* X, const double* coef, int32_t n_in, double* out_val,
+                            int64_t* out_log2, uint32_t* flags, void* ws, Plan& P, size_t* need) {
+  if (!X) return fail(HT_EINVAL, "X is NULL");
+  SumInfo S;
+  ht_status st = sum_info(X, coef, n_in, S);
+  if (st) return st;
+  Tree tr(X[0].d);
+  Arena A(ws);
+  OrthOut O;
+  plan_orth(P, tr, S, HT_PREC_FP64, A, O, {}, false, nullptr, nullptr, false, /*form_qo=*/false);
+  if (need) *need = align256(A.off) + 256;
+  if (!ws) return HT_OK;
+  g_label = "norm_root";
+  PhiRec r = blank_phi();
+  r.P = O.BDo; r.n = (int64_t)S.K[tr.son1[0]] * S.K[tr.son2[0]];
+  r.out_val = out_val; r.out_log2 = reinterpret_cast<long long*>(out_log2);
+  r.add_dev = &O.st->log2_scale; r.flags = flags; r.mode = 2;
+  add_phi(P, {r});
+  if (flags) {
+    g_label = "finish";
+    StateRec w = blank_state(O.st);
+    w.flags = flags;
+    add_state(P, OP_WRITESCALE, {w});
+  }
+  return HT_OK;
+}
+
+ht_status ht_inner_workspace(ht_context* ctx, const ht_desc* X, const ht_desc* Y, size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(HT_EINVAL, "bytes is NULL");
+  if (!X || !Y) return fail(HT_EINVAL, "X or Y is NULL");
+  ht_status st;
+  if ((st = check_desc(X, "X", false)) || (st = check_desc(Y, "Y", false))) return st;
+  Placeholder px(X), py(Y);
+  Plan P;
+  return build_inner(&px.d, &py.d, nullptr, nullptr, nullptr, nullptr, P, bytes);
+}
+
+ht_status ht_inner(ht_context* ctx, const ht_desc* X, const ht_desc* Y, double* out_val, int64_t* out_log2,
+                   uint32_t* flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  if (!out_val || !out_log2) return fail(HT_EINVAL, "out_val and out_log2 are required");
+  size_t need = 0;
+  ht_status st = ht_inner_workspace(ctx, X, Y, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_inner(X, Y, out_val, out_log2, flags, ws, P, nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
+ht_status ht_norm_workspace(ht_context* ctx, const ht_desc* X, int32_t n_in, size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(HT_EINVAL, "bytes is NULL");
+  if (!X) return fail(HT_EINVAL, "X is NULL");
+  if (n_in < 1 || n_in > MAX_SEG) return fail(HT_EINVAL, "n_in must be in [1, 8]");
+  std::vector<Placeholder> ph;
+  ph.reserve(n_in);
+  std::vector<ht_desc> xs;
+  for (int c = 0; c < n_in; ++c) {
+    ht_status s = check_desc(&X[c], "X[c]", false);
+    if (s) return s;
+    ph.emplace_back(&X[c]);
+    xs.push_back(ph.back().d);
+  }
+  Plan P;
+  return build_norm(xs.data(), nullptr, n_in, nullptr, nullptr, nullptr, nullptr, P, bytes);
+}
+
+ht_status ht_norm(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in, double* out_val,
+                  int64_t* out_log2, uint32_t* flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  if (!out_val || !out_log2) return fail(HT_EINVAL, "out_val and out_log2 are required");
+  size_t need = 0;
+  ht_status st = ht_norm_workspace(ctx, X, n_in, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(HT_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes, 256-byte aligned");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  st = build_norm(X, coef, n_in, out_val, out_log2, flags, ws, P, nullptr);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------------------ entries
 static size_t entries_chunk(const ht_desc* X, int64_t m, size_t* per_index) {
   Tree tr(X->d);
@@ -2688,6 +2977,22 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (en[i].expo1 && (s = check_range(en[i].expo1, 0, mc - 1, 4, w + " expo1"))) return s;
         if (en[i].expo2 && (s = check_range(en[i].expo2, 0, mc - 1, 4, w + " expo2"))) return s;
       }
+    } else if (op.kind == OP_PHI) {
+      const PhiRec* pr = reinterpret_cast<const PhiRec*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const PhiRec& r = pr[i];
+        const std::string w = tag + " phi record " + std::to_string(i);
+        if (r.n < 1 || (r.mode == 1 && r.n != 1)) return fail(HT_EINVAL, "validator: phi size " + w);
+        if ((s = check_range(r.P, 0, r.n - 1, 8, w + " P"))) return s;
+        if (r.E && (s = check_range(r.E, 0, 0, 8, w + " E"))) return s;
+        if (r.E1 && (s = check_range(r.E1, 0, 0, 8, w + " E1"))) return s;
+        if (r.E2 && (s = check_range(r.E2, 0, 0, 8, w + " E2"))) return s;
+        if (r.add_dev && (s = check_range(r.add_dev, 0, 0, 8, w + " add"))) return s;
+        if (r.flags && (s = check_range(r.flags, 0, 0, 4, w + " flags"))) return s;
+        if (r.mode >= 1 && ((s = check_range(r.out_val, 0, 0, 8, w + " out")) ||
+                            (s = check_range(r.out_log2, 0, 0, 8, w + " out_log2"))))
+          return s;
+      }
     } else if (op.kind == OP_EFINISH) {
       if ((s = check_range(op.p0, 0, op.c[0] - 1, 8, tag + " vals")) || (s = check_range(op.p1, 0, op.c[0] - 1, 4, tag + " expo")) ||
           (s = check_range(op.p2, 0, op.c[0] - 1, 8, tag + " out")))
@@ -2880,6 +3185,54 @@ ht_status ht_debug_validate_orthogonalize(const ht_desc* X, int32_t precision) {
   g_regions->pop_back();
   Plan P;
   st = build_orth(&fx.desc, precision, (int64_t*)scale, nullptr, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_inner(const ht_desc* X, const ht_desc* Y) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_inner_workspace(nullptr, X, Y, &need);
+  if (st) return st;
+  FakeSpace F;
+  Tree tr(X->d);
+  FakeTensor fx, fy;
+  std::vector<int> rx(X->rank, X->rank + tr.nn), ry(Y->rank, Y->rank + tr.nn);
+  fake_tensor(F, X, rx, X->frame_dtype, X->transfer_dtype, fx, "X");
+  fake_tensor(F, Y, ry, Y->frame_dtype, Y->transfer_dtype, fy, "Y");
+  void* val = F.get(8, "out_val");
+  void* lg = F.get(8, "out_log2");
+  void* flags = F.get(4, "flags");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  Plan P;
+  st = build_inner(&fx.desc, &fy.desc, (double*)val, (int64_t*)lg, (uint32_t*)flags, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_norm(const ht_desc* X, int32_t n_in) {
+  RegionScope scope;
+  size_t need = 0;
+  ht_status st = ht_norm_workspace(nullptr, X, n_in, &need);
+  if (st) return st;
+  FakeSpace F;
+  Tree tr(X[0].d);
+  std::vector<FakeTensor> fx(n_in);
+  std::vector<ht_desc> xs(n_in);
+  for (int c = 0; c < n_in; ++c) {
+    std::vector<int> rk(X[c].rank, X[c].rank + tr.nn);
+    fake_tensor(F, &X[c], rk, X[c].frame_dtype, X[c].transfer_dtype, fx[c], "X");
+    xs[c] = fx[c].desc;
+  }
+  void* val = F.get(8, "out_val");
+  void* lg = F.get(8, "out_log2");
+  void* flags = F.get(4, "flags");
+  void* ws = F.get(need, "ws-total");
+  g_regions->pop_back();
+  Plan P;
+  std::vector<double> coef(n_in, 1.0);
+  st = build_norm(xs.data(), coef.data(), n_in, (double*)val, (int64_t*)lg, (uint32_t*)flags, ws, P, nullptr);
   if (st) return st;
   return validate_plan(P, 0);
 }

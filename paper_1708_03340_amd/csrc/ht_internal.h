@@ -189,6 +189,30 @@ struct CopyRec {
   double alpha;
 };
 
+// Power-of-two bookkeeping of the inner product (Definition (phi)) and the
+// norm of an orthogonalised tensor (the Frobenius norm of its root matrix).
+//   mode 0: e = binary exponent of max |P[i]|; P <- P 2^-e;
+//           *E = e + (E1 ? *E1 : 0) + (E2 ? *E2 : 0).
+//   mode 1: like mode 0, then *out_val = P[0] and
+//           *out_log2 = *E + add + (add_dev ? *add_dev : 0) (P is 1 x 1).
+//   mode 2: v = ||P||_F (over n entries); *out_val = v 2^-e with e the
+//           exponent of v, *out_log2 = e + add + (add_dev ? *add_dev : 0).
+// A non-finite entry sets bit 1 of *flags (if flags is not NULL).
+struct PhiRec {
+  double* P;
+  int64_t n;
+  long long* E;
+  const long long* E1;
+  const long long* E2;
+  double* out_val;
+  long long* out_log2;
+  const long long* add_dev;
+  long long add;
+  unsigned int* flags;
+  int32_t mode, pad;
+};
+hipError_t launch_phi_scale(const PhiRec* r, int n, hipStream_t s);
+
 hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s);
 hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);
 hipError_t launch_chol(const SmallArgs* args, int n, int sweep, hipStream_t s, GlobalState* st);

@@ -157,6 +157,45 @@ __global__ void root_norm_kernel(const StateRec* __restrict__ recs) {
   }
 }
 
+// One workgroup per record (see PhiRec).
+__global__ void phi_scale_kernel(const PhiRec* __restrict__ recs) {
+  __shared__ double red[NT / 64];
+  const PhiRec& R = recs[blockIdx.x];
+  double mx = 0.0, ss = 0.0;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < R.n; i += NT) {
+    const double v = R.P[i];
+    if (!isfinite(v)) bad = true;
+    mx = fmax(mx, fabs(v));
+    ss = fma(v, v, ss);
+  }
+  const double m = wg_max(mx, red);
+  const double b = wg_max(bad ? 1.0 : 0.0, red);
+  if (R.mode == 2) {
+    const double tot = wg_sum(ss, red);
+    if (threadIdx.x == 0) {
+      const double v = sqrt(tot);
+      const int e = exp2_of(v);
+      *R.out_val = ldexp(v, -e);
+      *R.out_log2 = e + R.add + (R.add_dev ? *R.add_dev : 0);
+      if (b > 0.0 && R.flags) atomicOr(R.flags, 2u);
+    }
+    return;
+  }
+  const int e = exp2_of(m);
+  const double sc = ldexp(1.0, -e);
+  for (int64_t i = threadIdx.x; i < R.n; i += NT) R.P[i] *= sc;
+  if (threadIdx.x == 0) {
+    const long long E = e + (R.E1 ? *R.E1 : 0) + (R.E2 ? *R.E2 : 0);
+    if (R.E) *R.E = E;
+    if (R.mode == 1) {
+      *R.out_val = R.P[0];   // P is 1 x 1, scaled above by this thread
+      *R.out_log2 = E + R.add + (R.add_dev ? *R.add_dev : 0);
+    }
+    if (b > 0.0 && R.flags) atomicOr(R.flags, 2u);
+  }
+}
+
 __global__ void write_scale_kernel(const StateRec* __restrict__ recs, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -223,6 +262,12 @@ hipError_t launch_sigma_from_lam(const SmallArgs* args, int n, double* const* si
 hipError_t launch_root_norm(const StateRec* r, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(root_norm_kernel, dim3(n), dim3(NT), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_scale(const PhiRec* r, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(phi_scale_kernel, dim3(n), dim3(NT), 0, s, r);
   return hipGetLastError();
 }
 

@@ -22,7 +22,9 @@ def L():
     L.ht_debug_validate_entries.argtypes = [P(H.HtDesc), ctypes.c_int64]
     L.ht_debug_validate_truncate_batched.argtypes = [ctypes.c_int32, P(H.HtDesc), P(ctypes.c_int32),
                                                      P(H.HtTruncOpts), P(ctypes.c_int32)]
-    for f in ("truncate", "orthogonalize", "gramians", "entries", "truncate_batched"):
+    L.ht_debug_validate_inner.argtypes = [P(H.HtDesc), P(H.HtDesc)]
+    L.ht_debug_validate_norm.argtypes = [P(H.HtDesc), ctypes.c_int32]
+    for f in ("truncate", "orthogonalize", "gramians", "entries", "truncate_batched", "inner", "norm"):
         getattr(L, "ht_debug_validate_" + f).restype = ctypes.c_int
     return L
 
@@ -110,6 +112,24 @@ def test_gramians_plans_in_bounds(L, d, k):
                                      (2, 5, 3, 17), (9, 100, 64, 70000)])
 def test_entries_plans_in_bounds(L, d, n, k, m):
     check(L, L.ht_debug_validate_entries(ctypes.byref(desc(d, n, uniform(d, k))), m))
+
+
+@pytest.mark.parametrize("d,n,kx,ky,fx,fy", [(2, 5, 3, 2, 0, 0), (4, 16, 4, 7, 0, 1), (7, 33, 5, 9, 1, 1),
+                                            (16, 1000, 64, 32, 1, 0), (64, 10000, 128, 128, 1, 1),
+                                            (128, 100000, 64, 64, 1, 1), (5, 3, 8, 1, 0, 0)])
+def test_inner_plans_in_bounds(L, d, n, kx, ky, fx, fy):
+    """ht_inner (Definition (phi)) for ranks and dtypes that differ between
+    the two tensors."""
+    X = desc(d, n, uniform(d, kx), fx)
+    Y = desc(d, n, uniform(d, ky), fy)
+    check(L, L.ht_debug_validate_inner(ctypes.byref(X), ctypes.byref(Y)))
+
+
+@pytest.mark.parametrize("d,n,k,n_in", [(2, 5, 3, 1), (4, 16, 4, 2), (7, 33, 5, 3), (64, 10000, 64, 2),
+                                        (128, 100000, 64, 2), (3, 2, 9, 2)])
+def test_norm_plans_in_bounds(L, d, n, k, n_in):
+    X = (H.HtDesc * n_in)(*[desc(d, n, uniform(d, k)) for _ in range(n_in)])
+    check(L, L.ht_debug_validate_norm(X, n_in))
 
 
 def test_validator_catches_overrun(L):
