@@ -16,7 +16,10 @@ region (HIP events around every launch, on the stream it runs on) and
 `roofline_mfma` the matrix-core kernel with the largest share; `traffic` is
 the committed rocprofv3 counter figure while the kernel sources match it.
 `cpu_baseline` times the float64 NumPy oracle on one sum-truncation of the
-same workload on the host cores.  `large_single` times the large single
+same workload on the host cores.  `graph_ms_per_step` replays the headline step captured in a HIP graph.
+`batched` times 256 uneven sums in one ht_truncate_batched call.
+`inner_product` times <A, C> by Definition (phi) and the
+difference norm ||A - C|| on the same inputs.  `large_single` times the large single
 workload (d = 128, n = 1e5, k = 64 per summand, truncated to rank 64) and
 ht_entries of its result at 1e6 random multi-indices.
 """
@@ -123,7 +126,7 @@ def device_tensor(H, torch, d, n, k, spectrum, gen):
     orthonormal from QR of N(0,1) matrices), float64 root of the same form."""
     tr = H.ht_tree(d)
     nn = 2 * d - 1
-    g = torch.tensor(spectrum, dtype=torch.float64, device="cuda")
+    g = torch.tensor(spectrum, dtype=torch.float64, device="cuda") if spectrum is not None else None
 
     def orth(rows, cols):
         q, _ = torch.linalg.qr(torch.randn(rows, cols, dtype=torch.float64, device="cuda", generator=gen))
@@ -134,12 +137,76 @@ def device_tensor(H, torch, d, n, k, spectrum, gen):
         if int(tr["son1"][t]) < 0:
             leaves[int(tr["lo"][t])] = torch.randn(k, n, dtype=torch.float32, device="cuda", generator=gen)
             ranks[t] = k
+        elif spectrum is None:   # N(0,1) transfer tensors
+            shape = (k, k) if t == 0 else (k, k, k)
+            transfer[t] = torch.randn(*shape, dtype=torch.float64 if t == 0 else torch.float32, device="cuda",
+                                      generator=gen)
+            ranks[t] = 1 if t == 0 else k
         elif t == 0:
             transfer[t] = (orth(k, k) * g[None, :]) @ orth(k, k).T
         else:
             transfer[t] = ((orth(k, k) * g[None, :]) @ orth(k * k, k).T).reshape(k, k, k).float()
             ranks[t] = k
     return H.DeviceHT(d, [n] * d, ranks, leaves, transfer, 0)
+
+
+def batched(H, torch, steps=3):
+    """The batched workload: 256 independent sums A_b + C_b, d ~ U{4..32},
+    n ~ U[100, 4096], k ~ U{8..48} (the same meta draw as the tests), N(0,1)
+    float32 frames and transfer tensors drawn on the device, each truncated
+    to its own k in the mixed path by one ht_truncate_batched call."""
+    import htsynth as S
+    meta = S.batched_meta()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    problems = []
+    for m in meta:
+        A = device_tensor(H, torch, m["d"], m["n"], m["k"], None, gen)
+        C = device_tensor(H, torch, m["d"], m["n"], m["k"], None, gen)
+        problems.append(dict(Xs=[A, C], mode=H.HT_RANK_FIXED, ranks=[m["k"]] * (2 * m["d"] - 1),
+                             precision=H.HT_PREC_MIXED))
+    bt = H.BatchTruncator(problems)
+    bt()
+    t = timed(bt, steps, torch)
+    H.profile_enable(True)
+    H.profile_reset()
+    bt()
+    torch.cuda.synchronize()
+    prof = H.profile_read()
+    H.profile_enable(False)
+    H.profile_reset()
+    flops = sum(e["flops"] for e in prof)
+    launches = sum(e["launches"] for e in prof)
+    log(f"bench: batched 256 sums {t * 1e3:.2f} ms per batch, {launches} launches, "
+        f"{flops / t / 1e12:.2f} TF/s of algorithmic flops")
+    out = dict(workload="256 HT sums in one ht_truncate_batched call: d ~ U{4..32}, n ~ U[100,4096], "
+                        "k ~ U{8..48} per summand, each truncated to its own k (mixed precision)",
+               ms_per_batch=t * 1e3, value=256.0 / t, unit="sum-truncations/s", steps=steps,
+               launches_per_batch=launches, alg_flops=flops, achieved_tflops=flops / t / 1e12,
+               frac_fp64_peak=flops / t / PEAKS["double"])
+    del problems, bt
+    torch.cuda.empty_cache()
+    return out
+
+
+def graph_replay(H, torch, tr, steps):
+    """The same d=64 sum-truncation captured once in a HIP graph and replayed."""
+    tr()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        tr(stream=s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            tr(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g.replay()
+    t = timed(g.replay, steps, torch)
+    log(f"bench: graph replay {t * 1e3:.3f} ms/step")
+    return t
 
 
 def large_single(H, torch, steps=3):
@@ -169,6 +236,45 @@ def large_single(H, torch, steps=3):
                unit="sum-truncations/s", steps=steps, entries_m=m, entries_ms=t_ent * 1e3, entries_per_s=m / t_ent)
     del A, C, tr, res, idx
     torch.cuda.empty_cache()
+    return out
+
+
+def inner_products(H, torch, A, C, a, c, steps=20, with_cpu=True):
+    """<A, C> by Definition (phi) and the difference norm ||A - C|| (lazy sum
+    orthogonalised, root norm) on the d=64 workload; achieved float64 rate
+    from the launches' algorithmic flops; the oracle's <A, C> timed beside it."""
+    def phi():
+        return H.ht_inner(A, C)
+
+    def dn():
+        return H.ht_norm([A, C], [1.0, -1.0])
+
+    phi(); dn()
+    t_phi = timed(phi, steps, torch)
+    t_dn = timed(dn, steps, torch)
+    H.profile_enable(True)
+    H.profile_reset()
+    phi()
+    torch.cuda.synchronize()
+    prof = H.profile_read()
+    H.profile_enable(False)
+    H.profile_reset()
+    flops = sum(e["flops"] for e in prof)
+    kern_ms = sum(e["ms"] for e in prof)
+    out = dict(workload="<A, C> by Definition (phi), d=64 n=10000 k=64 (float32 frames), and ||A - C|| "
+                        "by orthogonalising the lazy difference",
+               inner_ms=t_phi * 1e3, inner_per_s=1.0 / t_phi, diff_norm_ms=t_dn * 1e3,
+               inner_alg_flops=flops, inner_achieved_tflops=flops / t_phi / 1e12,
+               inner_frac_fp64_peak=flops / t_phi / PEAKS["double"], inner_kernel_ms=kern_ms)
+    log(f"bench: <A,C> {t_phi * 1e3:.3f} ms ({flops / t_phi / 1e12:.2f} TF/s of algorithmic flops), "
+        f"||A - C|| {t_dn * 1e3:.3f} ms")
+    if with_cpu:
+        from oracle import ht_oracle as O
+        Ao, Co = O.from_input(a), O.from_input(c)
+        t0 = time.perf_counter()
+        O.inner(Ao, Co)
+        out["cpu_oracle_inner_s"] = time.perf_counter() - t0
+        log(f"bench: oracle <A,C> {out['cpu_oracle_inner_s']:.2f} s")
     return out
 
 
@@ -344,6 +450,9 @@ def main():
         "roofline": roof,
         "roofline_mfma": roof_mfma,
     }
+    out["graph_ms_per_step"] = graph_replay(H, torch, mixed, args.steps) * 1e3
+    out["inner_product"] = inner_products(H, torch, A, C, a, c, with_cpu=not args.no_cpu)
+    out["batched"] = None if args.no_large else batched(H, torch)
     out["large_single"] = None if args.no_large else large_single(H, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline (one sum-truncation)")
