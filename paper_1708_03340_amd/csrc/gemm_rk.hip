@@ -19,6 +19,8 @@
 // are both contiguous along their row index stages its chunks k-major (a
 // chunk row holds 128 consecutive rows): each load instruction then reads
 // 512 contiguous bytes and each LDS write covers all banks once.
+#include <type_traits>
+
 #include "ht_internal.h"
 
 namespace ht {
@@ -83,71 +85,80 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   const TA* Ab = reinterpret_cast<const TA*>(D.A);
   const TB* Bb = reinterpret_cast<const TB*>(D.B);
   const int msplit = D.msplit > 0 ? D.msplit : M;   // rows from here on lie a2off further
-  // element (r, k) of A in chunk segment kb
-  auto aget = [&](int kb, int r, int k) -> TM {
+  // offset of element (r, k) of A in chunk segment kb (row and k clamped, so
+  // every load is in bounds; entries past K are masked when stashed)
+  auto aoff = [&](int kb, int r, int k) -> int64_t {
     const int rr = min(r, M - 1);
-    const int64_t off = (int64_t)kb * D.sAkb + (int64_t)rr * D.sAm + (rr >= msplit ? D.a2off : 0) +
-                        (int64_t)min(k, K - 1) * D.sAk;
-    return (TM)gld(&Ab[off]) * (TM)(k < K);
+    return (int64_t)kb * D.sAkb + (int64_t)rr * D.sAm + (rr >= msplit ? D.a2off : 0) +
+           (int64_t)min(k, K - 1) * D.sAk;
   };
 
   // loader coordinates: along k (thread t: k t % KC of rows t / KC + (256 / KC) u,
   // so that KC consecutive lanes read one row's chunk and write one LDS row)
-  // or along the row index (thread t: k t/(128/LU), LU rows from (t%(128/LU))*LU)
+  // or along the row index (thread t: k t/(128/LU), LU rows from (t%(128/LU))*LU).
+  // The prefetched values stay raw (operand type, unmasked) until the chunk
+  // is stashed after the current chunk's products, so nothing before those
+  // products waits for them.
   constexpr int RG = 128 / LU;
   constexpr int KR = 256 / RK_KC;   // rows per pass of the k-contiguous loader
-  TM ra[LU], rb[LU];
+  TA ra[LU];
+  TB rb[LU];
+  auto kof = [&](int u) -> int {   // k within the chunk of this thread's value u
+    if constexpr (KM) return (tid >> 7) * LU + u;
+    return a_kc ? tid % RK_KC : tid / RG;
+  };
+  auto kofb = [&](int u) -> int {
+    if constexpr (KM) return (tid >> 7) * LU + u;
+    return b_kc ? tid % RK_KC : tid / RG;
+  };
   auto load = [&](int c) {
     const int kb = c / cpb, k0 = (c % cpb) * RK_KC;
+    const TB* Bg = Bb + (int64_t)kb * D.sBkb;
     if constexpr (KM) {   // thread t: row t % 128, k from (t / 128) * LU
 #pragma unroll
-      for (int u = 0; u < LU; ++u) ra[u] = aget(kb, tid & 127, k0 + (tid >> 7) * LU + u);
-      const TB* Bk = Bb + (int64_t)kb * D.sBkb;
+      for (int u = 0; u < LU; ++u) ra[u] = gld(&Ab[aoff(kb, tid & 127, k0 + kof(u))]);
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
-        const int n = tid & 127, k = k0 + (tid >> 7) * LU + u;
-        rb[u] = (TM)gld(&Bk[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]) * (TM)(k < K);
+        const int n = tid & 127, k = k0 + kofb(u);
+        rb[u] = gld(&Bg[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]);
       }
       return;
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
       const int r = a_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
-      const int k = a_kc ? k0 + tid % RK_KC : k0 + tid / RG;
-      ra[u] = aget(kb, r, k);
+      ra[u] = gld(&Ab[aoff(kb, r, k0 + kof(u))]);
     }
     if (!SAMEB) {
-      const TB* Bk = Bb + (int64_t)kb * D.sBkb;
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
         const int n = b_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
-        const int k = b_kc ? k0 + tid % RK_KC : k0 + tid / RG;
-        const TM v = (TM)gld(&Bk[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]);
-        rb[u] = v * (TM)(k < K);
+        const int k = k0 + kofb(u);
+        rb[u] = gld(&Bg[(int64_t)min(k, K - 1) * D.sBk + (int64_t)min(n, N - 1) * D.sBn]);
       }
     }
   };
-  auto stash = [&](int buf) {
+  // converted to the math type and masked past K as they go to LDS
+  auto stash = [&](int buf, int c) {
+    const int k0 = (c % cpb) * RK_KC;
     if constexpr (KM) {
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
-        Ak[buf * KMB + (tid >> 7) * LU + u][tid & 127] = ra[u];
-        Bk[buf * KMB + (tid >> 7) * LU + u][tid & 127] = rb[u];
+        Ak[buf * KMB + (tid >> 7) * LU + u][tid & 127] = (TM)ra[u] * (TM)(k0 + kof(u) < K);
+        Bk[buf * KMB + (tid >> 7) * LU + u][tid & 127] = (TM)rb[u] * (TM)(k0 + kofb(u) < K);
       }
       return;
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
       const int r = a_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
-      const int k = a_kc ? tid % RK_KC : tid / RG;
-      As[buf][r][k] = ra[u];
+      As[buf][r][kof(u)] = (TM)ra[u] * (TM)(k0 + kof(u) < K);
     }
     if (!SAMEB) {
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
         const int n = b_kc ? tid / RK_KC + KR * u : (tid % RG) * LU + u;
-        const int k = b_kc ? tid % RK_KC : tid / RG;
-        Bs[buf][n][k] = rb[u];
+        Bs[buf][n][kofb(u)] = (TM)rb[u] * (TM)(k0 + kofb(u) < K);
       }
     }
   };
@@ -170,75 +181,80 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
   };
 
   load(c0);
-  stash(0);
+  stash(0, c0);
   __syncthreads();
   int buf = 0;
   if constexpr (SAMEB) {
     // Gram matrix: block rows w and 7-w against the block columns right of
     // them; the column fragments of one step are read once and serve both
-    // rows (the skipped blocks are uniform per wave)
-    V acc[2][8];
+    // rows.  The loop is compiled once per wave, so that each wave's block
+    // set is fixed at compile time and its products run without branches.
+    auto gram = [&](auto wc) {
+      constexpr int W = decltype(wc)::value;
+      V acc[2][8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[i][j] = V{0, 0, 0, 0};
-    for (int c = c0; c < c1; ++c) {
-      const bool more = c + 1 < c1;
-      if (more) load(c + 1);
+        for (int j = 0; j < 8; ++j) acc[i][j] = V{0, 0, 0, 0};
+      for (int c = c0; c < c1; ++c) {
+        const bool more = c + 1 < c1;
+        if (more) load(c + 1);
 #pragma unroll
-      for (int st = 0; st < RK_KC / 16; ++st) {
-        const int kq = 16 * st + 4 * (lane >> 4);
+        for (int st = 0; st < RK_KC / 16; ++st) {
+          const int kq = 16 * st + 4 * (lane >> 4);
 #pragma unroll
-        for (int hq = 0; hq < 2; ++hq) {
-          TM fa[2][2], fb[8][2];
+          for (int hq = 0; hq < 2; ++hq) {
+            TM fa[2][2];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const TM* p = &As[buf][16 * (i == 0 ? wave : 7 - wave) + (lane & 15)][kq + 2 * hq];
-            fa[i][0] = p[0];
-            fa[i][1] = p[1];
+            for (int i = 0; i < 2; ++i) {
+              const TM* p = &As[buf][16 * (i == 0 ? W : 7 - W) + (lane & 15)][kq + 2 * hq];
+              fa[i][0] = p[0];
+              fa[i][1] = p[1];
+            }
+            // block columns left of both rows are skipped; a column's two
+            // fragments are read just before its products
+#pragma unroll
+            for (int j = W; j < 8; ++j) {
+              if (PART && j >= nbk) continue;   // block column past the result (its row is at most j)
+              const TM* p = &As[buf][16 * j + (lane & 15)][kq + 2 * hq];
+              const TM fb0 = p[0], fb1 = p[1];
+#pragma unroll
+              for (int i = 0; i < 2; ++i)
+                if (j >= (i == 0 ? W : 7 - W)) acc[i][j] = Tr::mfma(fa[i][0], fb0, acc[i][j]);
+#pragma unroll
+              for (int i = 0; i < 2; ++i)
+                if (j >= (i == 0 ? W : 7 - W)) acc[i][j] = Tr::mfma(fa[i][1], fb1, acc[i][j]);
+            }
           }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            if (j < wave) continue;   // block columns left of both rows
-            const TM* p = &As[buf][16 * j + (lane & 15)][kq + 2 * hq];
-            fb[j][0] = p[0];
-            fb[j][1] = p[1];
-          }
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                if (i == 1 && j < 4) continue;   // block row 7-w >= 4: never left of 4
-                if (j < (i == 0 ? wave : 7 - wave)) continue;
-                if (PART && j >= nbk) continue;   // block column past the result (its row is at most j)
-                acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
-              }
         }
+        if (more) stash(buf ^ 1, c + 1);
+        __syncthreads();
+        buf ^= 1;
       }
-      if (more) stash(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+      const double alpha = scale();
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = (i == 0 ? W : 7 - W); j < 8; ++j) {
+          const int rbk = i == 0 ? W : 7 - W;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = 16 * rbk + Tr::row(v, lane), n = 16 * j + (lane & 15);
+            if (m < M && n < N) {
+              const double val = alpha * (double)acc[i][j][v];
+              put(m, n, val);
+              if (j != rbk) put(n, m, val);
+            }
+          }
+        }
+    };
+    switch (__builtin_amdgcn_readfirstlane(wave)) {
+      case 0: gram(std::integral_constant<int, 0>{}); break;
+      case 1: gram(std::integral_constant<int, 1>{}); break;
+      case 2: gram(std::integral_constant<int, 2>{}); break;
+      case 3: gram(std::integral_constant<int, 3>{}); break;
+      default: __builtin_unreachable();
     }
-    const double alpha = scale();
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int rbk = i == 0 ? wave : 7 - wave;
-        if (i == 1 && j < 4) continue;
-        if (j < rbk) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = 16 * rbk + Tr::row(v, lane), n = 16 * j + (lane & 15);
-          if (m < M && n < N) {
-            const double val = alpha * (double)acc[i][j][v];
-            put(m, n, val);
-            if (j != rbk) put(n, m, val);
-          }
-        }
-      }
   } else if constexpr (SYM) {
     // symmetric result of two operands: the wave's nine blocks, row block w
     // against columns w..7, then row block 7-w against columns 7-w..7 (36
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
           }
         }
       }
-      if (more) stash(buf ^ 1);
+      if (more) stash(buf ^ 1, c + 1);
       __syncthreads();
       buf ^= 1;
     }
@@ -345,7 +361,7 @@ __global__ __launch_bounds__(RK_NT, MODE != 0 ? 2 : 1) void gemm_rk_kernel(const
               for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][q], fb[j][q], acc[i][j]);
         }
       }
-      if (more) stash(buf ^ 1);
+      if (more) stash(buf ^ 1, c + 1);
       __syncthreads();
       buf ^= 1;
     }
