@@ -243,11 +243,8 @@ def inner_products(H, torch, A, C, a, c, steps=20, with_cpu=True):
     """<A, C> by Definition (phi) and the difference norm ||A - C|| (lazy sum
     orthogonalised, root norm) on the d=64 workload; achieved float64 rate
     from the launches' algorithmic flops; the oracle's <A, C> timed beside it."""
-    def phi():
-        return H.ht_inner(A, C)
-
-    def dn():
-        return H.ht_norm([A, C], [1.0, -1.0])
+    phi = H.Inner(A, C)
+    dn = H.Norm([A, C], [1.0, -1.0])
 
     phi(); dn()
     t_phi = timed(phi, steps, torch)

@@ -275,6 +275,22 @@ ht_status ht_norm_workspace(ht_context* ctx, const ht_desc* X, int32_t n_in, siz
 ht_status ht_norm(ht_context* ctx, const ht_desc* X, const double* coef, int32_t n_in, double* out_val,
                   int64_t* out_log2, uint32_t* flags, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- operator application
+ * C = L A for an H-operator L and an H-tensor A on the same tree (Section
+ * 3.6, Lemma (operator)).  L is passed as an ht_desc whose mode mu has
+ * n_mu^2 rows (square operators): column r of its leaf frame is the matrix
+ * W_{mu,r} (n_mu x n_mu) stored row-major, entry (j, i) at row j * n_mu + i
+ * (the index pair (j_mu, i_mu) of eq. (operatorastensor)); its transfer
+ * tensors H_t and root are as for any HT tensor.  C (caller-allocated) must
+ * have A's mode sizes and ranks k^L_t k^A_t; C gets the leaf frames
+ * V_mu[:, r k_mu + l] = W_{mu,r} U_mu[:, l] and the transfer tensors
+ * F_t = H_t (x) B_t with F_t[(p,i)][(q,j)][(r,l)] = H_t[p][q][r] B_t[i][j][l]
+ * (operator index slowest; the root likewise).  C's scale is not written:
+ * the represented tensor is 2^(L.log2_scale + A.log2_scale) times C's data.
+ * Products in float64; C may be float32 or float64.  No workspace.  Errors:
+ * HT_EINVAL, HT_ESHAPE. */
+ht_status ht_apply(ht_context* ctx, const ht_desc* L, const ht_desc* A, const ht_desc* C, void* stream);
+
 /* ---------------------------------------------------------------- entries
  * A[i_1..i_d] for m multi-indices (Section 3.1): leaves pick row i_mu, inner
  * nodes apply eq. (transfermult), the root the root formula; evaluated level

@@ -31,6 +31,7 @@ ht_status ht_debug_validate_gramians(const ht_desc* X);
 ht_status ht_debug_validate_entries(const ht_desc* X, int64_t m);
 ht_status ht_debug_validate_inner(const ht_desc* X, const ht_desc* Y);
 ht_status ht_debug_validate_norm(const ht_desc* X, int32_t n_in);
+ht_status ht_debug_validate_apply(const ht_desc* L, const ht_desc* A);
 #ifdef __cplusplus
 }
 #endif

@@ -418,6 +418,13 @@ def truncate(X: HT, *, mode: str = "fixed", ranks=None, eps: float = 0.0, relati
         else:
             s1, s2 = tr.sons[0]
             T.B[0] = Qr[s1].T @ Xo.B[0] @ Qr[s2]
+    # the result's root in units of 2^e, e the binary exponent of ||B_D||_F
+    # of the orthogonalised tensor: an exact power-of-two rescaling that keeps
+    # repeatedly truncated tensors (the iterates of Algorithms (CG) and
+    # (richardson)) away from the floating-point range limits
+    eD = _exp2(float(np.linalg.norm(Xo.B[0])))
+    T.B[0] = np.ldexp(T.B[0], -eD)
+    T.log2_scale += eD
     sigma = {t: np.sqrt(lam[t]) for t in lam}
     info = dict(ranks=r, lam=lam, sigma=sigma, gram_log2=g, norm_units=norm_units, Xo=Xo)
     return T, info

@@ -29,7 +29,7 @@ EXPORTS = [
     "ht_tree", "ht_add", "ht_orthogonalize_workspace", "ht_orthogonalize", "ht_gramians_workspace",
     "ht_gramians", "ht_truncate_workspace", "ht_truncate", "ht_truncate_batched_workspace",
     "ht_truncate_batched", "ht_entries_workspace", "ht_entries", "ht_truncate_noalloc",
-    "ht_inner_workspace", "ht_inner", "ht_norm_workspace", "ht_norm",
+    "ht_inner_workspace", "ht_inner", "ht_norm_workspace", "ht_norm", "ht_apply",
     "ht_profile_enable", "ht_profile_read", "ht_profile_reset",
 ]
 
@@ -108,6 +108,7 @@ def lib(path: Optional[str] = None):
     L.ht_inner.argtypes = [VP, P(HtDesc), P(HtDesc), VP, VP, VP, VP, ctypes.c_size_t, VP]
     L.ht_norm_workspace.argtypes = [VP, P(HtDesc), I32, P(ctypes.c_size_t)]
     L.ht_norm.argtypes = [VP, P(HtDesc), P(ctypes.c_double), I32, VP, VP, VP, VP, ctypes.c_size_t, VP]
+    L.ht_apply.argtypes = [VP, P(HtDesc), P(HtDesc), P(HtDesc), VP]
     L.ht_truncate_batched_workspace.argtypes = [VP, I32, P(HtDesc), P(I32), P(HtTruncOpts), P(ctypes.c_size_t)]
     L.ht_truncate_batched.argtypes = [VP, I32, P(HtDesc), P(I32), P(ctypes.c_double), P(HtTruncOpts), P(HtDesc),
                                       P(VP), VP, VP, P(VP), VP, ctypes.c_size_t, VP]
@@ -571,44 +572,83 @@ class Scaled:
         return float(np.log2(abs(m)) + e) if m != 0.0 else float("-inf")
 
 
+class Inner:
+    """Reusable ht_inner call: descriptors, workspace and result buffers are
+    set up once; __call__ enqueues <X, Y> (Definition (phi)) on the stream."""
+
+    def __init__(self, X: DeviceHT, Y: DeviceHT, ctx=None):
+        import torch
+        self.ctx = ctx or ht_create_context()
+        self.X, self.Y = X, Y
+        self.dx, self.dy = X.desc(), Y.desc()
+        need = ctypes.c_size_t(0)
+        _check(lib().ht_inner_workspace(self.ctx.h, ctypes.byref(self.dx), ctypes.byref(self.dy),
+                                        ctypes.byref(need)))
+        self.ws = _ws(need.value)
+        self.m = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.e = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def __call__(self, stream=None) -> Scaled:
+        _check(lib().ht_inner(self.ctx.h, ctypes.byref(self.dx), ctypes.byref(self.dy), _ptr(self.m), _ptr(self.e),
+                              _ptr(self.flags), _ptr(self.ws), self.ws.numel(), _stream_ptr(stream)))
+        return Scaled(self.m, self.e, self.flags)
+
+
+class Norm:
+    """Reusable ht_norm call for the lazy sum sum_c coef[c] Xs[c]."""
+
+    def __init__(self, Xs, coef=None, ctx=None):
+        import torch
+        self.ctx = ctx or ht_create_context()
+        self.Xs = [Xs] if isinstance(Xs, DeviceHT) else list(Xs)
+        self.arr, self._keep = _descs(self.Xs)
+        self.cf = (ctypes.c_double * len(self.Xs))(*([1.0] * len(self.Xs) if coef is None else list(coef)))
+        need = ctypes.c_size_t(0)
+        _check(lib().ht_norm_workspace(self.ctx.h, self.arr, len(self.Xs), ctypes.byref(need)))
+        self.ws = _ws(need.value)
+        self.m = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.e = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def __call__(self, stream=None) -> Scaled:
+        _check(lib().ht_norm(self.ctx.h, self.arr, self.cf, len(self.Xs), _ptr(self.m), _ptr(self.e),
+                             _ptr(self.flags), _ptr(self.ws), self.ws.numel(), _stream_ptr(stream)))
+        return Scaled(self.m, self.e, self.flags)
+
+
 def ht_inner(X: DeviceHT, Y: DeviceHT, ctx=None, stream=None) -> Scaled:
     """<X, Y> by Definition (phi) / Lemma (phi), enqueued on the current stream."""
-    import torch
-    ctx = ctx or ht_create_context()
-    dx, dy = X.desc(), Y.desc()
-    need = ctypes.c_size_t(0)
-    _check(lib().ht_inner_workspace(ctx.h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(need)))
-    ws = _ws(need.value)
-    m = torch.zeros(1, dtype=torch.float64, device="cuda")
-    e = torch.zeros(1, dtype=torch.int64, device="cuda")
-    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
-    _check(lib().ht_inner(ctx.h, ctypes.byref(dx), ctypes.byref(dy), _ptr(m), _ptr(e), _ptr(flags), _ptr(ws),
-                          ws.numel(), _stream_ptr(stream)))
-    res = Scaled(m, e, flags)
-    res._ws = ws
+    f = Inner(X, Y, ctx)
+    res = f(stream)
+    res._ws = f.ws
     return res
 
 
 def ht_norm(Xs, coef=None, ctx=None, stream=None) -> Scaled:
     """||sum_c coef[c] Xs[c]|| through the orthogonalised lazy sum (Section 3.4);
     ht_norm([A, B], [1, -1]) is the difference norm."""
-    import torch
-    ctx = ctx or ht_create_context()
-    if isinstance(Xs, DeviceHT):
-        Xs = [Xs]
-    arr, keep = _descs(Xs)
-    cf = (ctypes.c_double * len(Xs))(*([1.0] * len(Xs) if coef is None else list(coef)))
-    need = ctypes.c_size_t(0)
-    _check(lib().ht_norm_workspace(ctx.h, arr, len(Xs), ctypes.byref(need)))
-    ws = _ws(need.value)
-    m = torch.zeros(1, dtype=torch.float64, device="cuda")
-    e = torch.zeros(1, dtype=torch.int64, device="cuda")
-    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
-    _check(lib().ht_norm(ctx.h, arr, cf, len(Xs), _ptr(m), _ptr(e), _ptr(flags), _ptr(ws), ws.numel(),
-                         _stream_ptr(stream)))
-    res = Scaled(m, e, flags)
-    res._ws = ws
+    f = Norm(Xs, coef, ctx)
+    res = f(stream)
+    res._ws = f.ws
     return res
+
+
+def ht_apply(L: DeviceHT, A: DeviceHT, C: Optional[DeviceHT] = None, ctx=None, stream=None,
+             frame_dtype=None, transfer_dtype=None) -> DeviceHT:
+    """C = L A by Lemma (operator).  L's mode mu has n_mu^2 rows (column r of
+    its leaf frame: the matrix W_{mu,r} row-major).  C is allocated with
+    ranks k^L_t k^A_t unless given; its scale is the sum of the two scales."""
+    ctx = ctx or ht_create_context()
+    if C is None:
+        ranks = [1] + [a * b for a, b in zip(L.ranks[1:], A.ranks[1:])]
+        inner = [b for t, b in enumerate(A.transfer) if b is not None and t != 0]
+        C = DeviceHT.empty(A.d, A.n, ranks, frame_dtype or A.leaves[0].dtype,
+                           transfer_dtype or (inner[0].dtype if inner else None))
+    dl, da, dc = L.desc(), A.desc(), C.desc()
+    _check(lib().ht_apply(ctx.h, ctypes.byref(dl), ctypes.byref(da), ctypes.byref(dc), _stream_ptr(stream)))
+    C.log2_scale = L.scale_value() + A.scale_value()
+    return C
 
 
 # ---------------------------------------------------------------- profiling

@@ -73,7 +73,7 @@ namespace {
 
 enum OpKind : int {
   OP_GEMM, OP_CHOL1, OP_CHOL2, OP_EIG, OP_RANK, OP_PROJPREP, OP_ROOTNORM, OP_FILL, OP_SETSTATE,
-  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_PHI,
+  OP_WRITESCALE, OP_COPY, OP_SIGMA, OP_EGATHER, OP_ENORM, OP_EFINISH, OP_PHI, OP_KRON,
   OP_FORK,   // the library's second stream waits for the caller's stream here
   OP_JOIN    // the caller's stream waits for everything on the second stream
 };
@@ -390,6 +390,19 @@ void add_phi(Plan& P, const std::vector<PhiRec>& r) {
   Op op;
   op.kind = OP_PHI;
   op.count = (int)r.size();
+  op.toff = put(P, r);
+  op.label = g_label;
+  op.stream = g_stream;
+  P.ops.push_back(op);
+}
+
+void add_kron(Plan& P, const std::vector<KronRec>& r) {
+  if (r.empty()) return;
+  Op op;
+  op.kind = OP_KRON;
+  op.count = (int)r.size();
+  for (const auto& k : r)
+    op.c[0] = std::max<int64_t>(op.c[0], (int64_t)k.P * k.Q * k.R * k.I * k.J * k.L);
   op.toff = put(P, r);
   op.label = g_label;
   op.stream = g_stream;
@@ -847,6 +860,9 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
       case OP_PHI:
         e = launch_phi_scale(reinterpret_cast<const PhiRec*>(tb + op.toff), op.count, stream);
         break;
+      case OP_KRON:
+        e = launch_kron(reinterpret_cast<const KronRec*>(tb + op.toff), op.count, op.c[0], stream);
+        break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     if (prof && ev0 && ev1) {
@@ -899,6 +915,7 @@ std::string kernel_name(const Op& op) {
     case OP_ENORM: return "normalize_kernel";
     case OP_EFINISH: return "finish_kernel";
     case OP_PHI: return "phi_scale_kernel";
+    case OP_KRON: return "kron_kernel";
     case OP_FORK: return "fork";
     case OP_JOIN: return "join";
   }
@@ -1164,7 +1181,16 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     add_gemm(P, dw, fdt, fdt, F64, MATH_F64, GEMM_ATOMIC, true, true);
     add_gemm(P, ds, fdt, fdt, F64, smath, GEMM_ATOMIC, true, true);
   }
-  auto small_args = [&](const std::vector<int>& nodes, double tol) {
+  // first sweeps shift G by 10 u (K + sqrt(rows)) trace(G), u the unit
+  // roundoff of the sweep's Gram products: above the rounding error of G and
+  // of its factorisation, so W R1^{-1} stays bounded for any W
+  const double shift_unit = prec == HT_PREC_MIXED ? 0x1p-24 : 0x1p-53;
+  auto sweep1_shift = [&](int t) {
+    const double rows = tr.son1[t] < 0 ? (double)X0.n[tr.mode(t)]
+                                       : (double)S.K[tr.son1[t]] * (double)S.K[tr.son2[t]];
+    return 10.0 * shift_unit * ((double)S.K[t] + std::sqrt(rows));
+  };
+  auto small_args = [&](const std::vector<int>& nodes, double tol, bool shift = false) {
     std::vector<SmallArgs> v;
     for (int t : nodes) {
       NodeBufs& b = O.nb[t];
@@ -1174,6 +1200,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
       a.G = b.G; a.G2 = b.G2; a.R1 = b.R1; a.Ri1 = b.Ri1;
       a.R = b.R; a.Ri = b.Ri; a.Rf = b.Rf;
       a.rf_type = T; a.tol_rel = tol;
+      a.shift_rel = shift ? sweep1_shift(t) : 0.0;
       a.Q = b.Q; a.lam = b.lam; a.Qm = b.Qm; a.QmT = b.QmT; a.rank_dev = b.rank; a.scratch = b.scratch;
       a.Bh = b.Bh;
       a.st = O.st;
@@ -1186,7 +1213,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
   {
     Op op;
     g_label = "leaf_chol1";
-    auto a = small_args(leaves, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
+    auto a = small_args(leaves, prec == HT_PREC_MIXED ? 1e-5 : 1e-12, true);
     add_small(P, OP_CHOL1, a);
     P.ops.back().p0 = O.st;
   }
@@ -1299,7 +1326,7 @@ void plan_orth(Plan& P, const Tree& tr, const SumInfo& S, int prec, Arena& A, Or
     }
     {
       g_label = "inner_chol1";
-      auto a = small_args(nodes, prec == HT_PREC_MIXED ? 1e-5 : 1e-12);
+      auto a = small_args(nodes, prec == HT_PREC_MIXED ? 1e-5 : 1e-12, true);
       add_small(P, OP_CHOL1, a);
       P.ops.back().p0 = O.st;
     }
@@ -1756,6 +1783,10 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
       h.B = O.nb[t2].Qm; h.sBk = O.nb[t2].rcap; h.sBn = 1;
       h.C = need ? nullptr : out->transfer[0]; h.sCm = O.nb[t2].rcap; h.sCn = 1;
       h.M = O.nb[t1].rcap; h.N = O.nb[t2].rcap; h.K = K2r;
+      // the result's root in units of 2^e_D (e_D goes to its scale): a
+      // truncated tensor comes out with a root of norm below 1 however many
+      // truncations it went through
+      h.alpha_dev = &O.st->alpha_root;
       r2.push_back(h);
       add_gemm(P, r2, F64, F64, F64, MATH_F64, GEMM_STORE, true, false);
     }
@@ -1795,6 +1826,7 @@ static ht_status build_truncate(ht_context* ctx, const ht_desc* X, const double*
     g_label = "finish";
     StateRec r = blank_state(O.st);
     r.out_scale = reinterpret_cast<long long*>(out_scale); r.flags = flags; r.root_rank = out_ranks;
+    r.add_eD = 1;
     add_state(P, OP_WRITESCALE, {r});
   }
   (void)tsz;
@@ -2509,6 +2541,66 @@ ht_status ht_norm(ht_context* ctx, const ht_desc* X, const double* coef, int32_t
   return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
 }
 
+// ------------------------------------------------------------------ operator application (Section 3.6)
+// C = L A by Lemma (operator): leaf frames V_mu[:, r k_mu + l] = W_{mu,r} U_mu[:, l]
+// (one batched product per leaf, a batch entry per operator rank r), and
+// every transfer tensor F_t = H_t (x) B_t (the operator index slowest).
+static ht_status build_apply(const ht_desc* L, const ht_desc* A, const ht_desc* C, Plan& P) {
+  ht_status st;
+  if ((st = check_desc(L, "L")) || (st = check_desc(A, "A")) || (st = check_desc(C, "C"))) return st;
+  const int d = A->d;
+  if (L->d != d || C->d != d) return fail(HT_ESHAPE, "L, A and C must share d");
+  Tree tr(d);
+  for (int mu = 0; mu < d; ++mu) {
+    const int64_t n = A->n[mu];
+    if (L->n[mu] != n * n) return fail(HT_ESHAPE, "operator frames must have n_mu^2 rows (square operators)");
+    if (C->n[mu] != n) return fail(HT_ESHAPE, "C must have the mode sizes of A");
+  }
+  for (int t = 1; t < tr.nn; ++t)
+    if (C->rank[t] != L->rank[t] * A->rank[t])
+      return fail(HT_ESHAPE, "C's ranks must be the products of L's and A's (node " + std::to_string(t) + ")");
+  g_label = "apply_leaf";
+  std::vector<GemmDesc> dl;
+  for (int mu = 0; mu < d; ++mu) {
+    const int t = tr.leaf_node[mu];
+    const int64_t n = A->n[mu];
+    GemmDesc g = blank_desc();
+    g.A = L->leaf[mu]; g.sAm = n; g.sAk = 1; g.sAb = L->leaf_ld[mu];       // W_{mu,r}[j][i]
+    g.B = A->leaf[mu]; g.sBk = 1; g.sBn = A->leaf_ld[mu];                  // U_mu[i][l]
+    g.C = C->leaf[mu]; g.sCm = 1; g.sCn = C->leaf_ld[mu];                  // V_mu[j][r k + l]
+    g.sCb = (int64_t)A->rank[t] * C->leaf_ld[mu];
+    g.M = (int)n; g.N = A->rank[t]; g.K = (int)n; g.nbatch = L->rank[t];
+    dl.push_back(g);
+  }
+  add_gemm(P, dl, L->frame_dtype, A->frame_dtype, C->frame_dtype, MATH_F64, GEMM_STORE, true, true);
+  g_label = "apply_transfer";
+  std::vector<KronRec> kr;
+  for (int t = 0; t < tr.nn; ++t) {
+    if (tr.is_leaf(t)) continue;
+    const int s1 = tr.son1[t], s2 = tr.son2[t];
+    KronRec r;
+    std::memset(&r, 0, sizeof(r));
+    r.H = L->transfer[t]; r.B = A->transfer[t]; r.F = C->transfer[t];
+    r.tH = t == 0 ? F64 : L->transfer_dtype;
+    r.tB = t == 0 ? F64 : A->transfer_dtype;
+    r.tF = t == 0 ? F64 : C->transfer_dtype;
+    r.P = t == 0 ? 1 : L->rank[t]; r.Q = L->rank[s1]; r.R = L->rank[s2];
+    r.I = t == 0 ? 1 : A->rank[t]; r.J = A->rank[s1]; r.L = A->rank[s2];
+    kr.push_back(r);
+  }
+  add_kron(P, kr);
+  return HT_OK;
+}
+
+ht_status ht_apply(ht_context* ctx, const ht_desc* L, const ht_desc* A, const ht_desc* C, void* stream) {
+  if (!ctx) return fail(HT_EINVAL, "ctx is NULL");
+  HT_HIP(hipSetDevice(ctx->device));
+  Plan P;
+  ht_status st = build_apply(L, A, C, P);
+  if (st) return st;
+  return run_plan(ctx, P, reinterpret_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------------------ entries
 static size_t entries_chunk(const ht_desc* X, int64_t m, size_t* per_index) {
   Tree tr(X->d);
@@ -2977,6 +3069,18 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         if (en[i].expo1 && (s = check_range(en[i].expo1, 0, mc - 1, 4, w + " expo1"))) return s;
         if (en[i].expo2 && (s = check_range(en[i].expo2, 0, mc - 1, 4, w + " expo2"))) return s;
       }
+    } else if (op.kind == OP_KRON) {
+      const KronRec* kr = reinterpret_cast<const KronRec*>(at(op.toff));
+      for (int i = 0; i < op.count; ++i) {
+        const KronRec& r = kr[i];
+        const std::string w = tag + " kron record " + std::to_string(i);
+        const int64_t nh = (int64_t)r.P * r.Q * r.R, nb = (int64_t)r.I * r.J * r.L;
+        if (nh < 1 || nb < 1 || nh * nb > op.c[0]) return fail(HT_EINVAL, "validator: kron size " + w);
+        if ((s = check_range(r.H, 0, nh - 1, esize(r.tH), w + " H")) ||
+            (s = check_range(r.B, 0, nb - 1, esize(r.tB), w + " B")) ||
+            (s = check_range(r.F, 0, nh * nb - 1, esize(r.tF), w + " F")))
+          return s;
+      }
     } else if (op.kind == OP_PHI) {
       const PhiRec* pr = reinterpret_cast<const PhiRec*>(at(op.toff));
       for (int i = 0; i < op.count; ++i) {
@@ -3233,6 +3337,22 @@ ht_status ht_debug_validate_norm(const ht_desc* X, int32_t n_in) {
   Plan P;
   std::vector<double> coef(n_in, 1.0);
   st = build_norm(xs.data(), coef.data(), n_in, (double*)val, (int64_t*)lg, (uint32_t*)flags, ws, P, nullptr);
+  if (st) return st;
+  return validate_plan(P, 0);
+}
+
+ht_status ht_debug_validate_apply(const ht_desc* L, const ht_desc* A) {
+  RegionScope scope;
+  FakeSpace F;
+  Tree tr(A->d);
+  FakeTensor fl, fa, fc;
+  std::vector<int> rl(L->rank, L->rank + tr.nn), ra(A->rank, A->rank + tr.nn), rc(tr.nn, 1);
+  for (int t = 1; t < tr.nn; ++t) rc[t] = rl[t] * ra[t];
+  fake_tensor(F, L, rl, L->frame_dtype, L->transfer_dtype, fl, "L");
+  fake_tensor(F, A, ra, A->frame_dtype, A->transfer_dtype, fa, "A");
+  fake_tensor(F, A, rc, A->frame_dtype, A->transfer_dtype, fc, "C");
+  Plan P;
+  ht_status st = build_apply(&fl.desc, &fa.desc, &fc.desc, P);
   if (st) return st;
   return validate_plan(P, 0);
 }

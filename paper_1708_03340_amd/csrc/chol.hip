@@ -5,8 +5,9 @@
 // Section 3.4 asks for a reduced QR of every leaf frame and of M_{2,3}(B_t);
 // CholeskyQR2 gets R from two Gram matrices: G = W^T W = R1^T R1, then
 // G2 = (W R1^{-1})^T (W R1^{-1}) = R2^T R2 and R = R2 R1.
-//  * sweep 1 clamps pivots that fall below tol (a Gram matrix formed in
-//    float32 may be indefinite); the second sweep repairs R;
+//  * sweep 1 factors G + s I, s a small multiple of the rounding error of G
+//    (shifted CholeskyQR, Fukaya et al. 2020), and clamps pivots that still
+//    fall below tol; the second sweep repairs R;
 //  * sweep 2 drops the rows whose pivot vanishes (rank-deficient frames such
 //    as those of the sum A + A) and flags them.
 //
@@ -85,14 +86,27 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   for (int i = tid; i < KMAX; i += NT) dropped[i] = 0;
   if (tid == 0) any = 0;
   __syncthreads();
-  double md = 0.0;
+  double md = 0.0, tr = 0.0;
   for (int i = tid; i < K; i += NT) {
     const double v = L[i * LDL + i];
-    if (isfinite(v)) md = fmax(md, v);
+    if (isfinite(v)) {
+      md = fmax(md, v);
+      tr += fmax(v, 0.0);
+    }
   }
-  const double maxd = wg_max(md, red);
+  double maxd = wg_max(md, red);
   const double badany = wg_max(bad ? 1.0 : 0.0, red);
   if (badany > 0.0 && tid == 0) atomicOr(&st->flags, 2u);
+  if (sweep == 1 && a.shift_rel > 0.0) {
+    // shifted first sweep: R1^T R1 = G + s I with s above the rounding error
+    // of G and of the factorisation, so that ||W R1^{-1}|| stays near 1 when
+    // W is rank-deficient or ill-conditioned (an unshifted factor of such a
+    // G can have an inverse of any size); the second sweep restores R
+    const double s = a.shift_rel * wg_sum(tr, red);
+    for (int i = tid; i < K; i += NT) L[i * LDL + i] += s;
+    maxd += s;
+    __syncthreads();
+  }
   const double tol = maxd > 0.0 ? a.tol_rel * maxd : 1.0;
 
   for (int p = 0; p < NB; ++p) {

@@ -140,6 +140,7 @@ struct SmallArgs {
   double* R;               // K x K upper factor R2 R1 (output, normalised by 2^-e)
   double* Ri;              // K x K inverse of the unnormalised factor
   double tol_rel;          // pivot tolerance relative to the largest diagonal entry
+  double shift_rel;        // first sweep: diagonal shift relative to trace(G)
   void* Rf;                // K x K copy of R in the forward-product type
   int32_t rf_type;         // DType of Rf
   int32_t clamp_only;      // 1: first sweep (clamp tiny pivots), 0: final
@@ -162,6 +163,7 @@ struct GlobalState {       // device-resident per-call scalars
   long long e_D;           // binary exponent of ||B_D||_F
   double norm2_units;      // ||A||^2 in Gramian units (trace of Bhat_t1)
   double thr;              // tolerance threshold in Gramian units
+  double alpha_root;       // 2^(-e_D): the truncated root is written in these units
 };
 
 // One tensor's scalars for the state kernels; a launch takes an array of
@@ -212,6 +214,20 @@ struct PhiRec {
   int32_t mode, pad;
 };
 hipError_t launch_phi_scale(const PhiRec* r, int n, hipStream_t s);
+
+// Kronecker product of two transfer tensors (Lemma (operator)):
+// F[(p,i)][(q,j)][(r,l)] = H[p][q][r] * B[i][j][l], the first factor's index
+// slowest; H is P x Q x R, B is I x J x L, all row-major (a root matrix has
+// P = I = 1).
+struct KronRec {
+  const void* H;
+  const void* B;
+  void* F;
+  int32_t tH, tB, tF;
+  int32_t P, Q, R, I, J, L;
+  int32_t pad;
+};
+hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, hipStream_t s);
 
 hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s);
 hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);

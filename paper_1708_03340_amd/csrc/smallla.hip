@@ -133,6 +133,7 @@ __global__ void set_state_kernel(const StateRec* __restrict__ recs, int n) {
   st->e_D = 0;
   st->norm2_units = 0.0;
   st->thr = 0.0;
+  st->alpha_root = 1.0;
 }
 
 __global__ void root_norm_kernel(const StateRec* __restrict__ recs) {
@@ -153,6 +154,7 @@ __global__ void root_norm_kernel(const StateRec* __restrict__ recs) {
     const int e = exp2_of(sqrt(tot));
     R.st->e_D = e;
     R.st->alpha_gram = ldexp(1.0, -2 * e);
+    R.st->alpha_root = ldexp(1.0, -e);
     if (b > 0.0) atomicOr(&R.st->flags, 2u);
   }
 }
@@ -193,6 +195,24 @@ __global__ void phi_scale_kernel(const PhiRec* __restrict__ recs) {
       *R.out_log2 = E + R.add + (R.add_dev ? *R.add_dev : 0);
     }
     if (b > 0.0 && R.flags) atomicOr(R.flags, 2u);
+  }
+}
+
+__device__ __forceinline__ double ld_any(const void* p, int t, int64_t i) {
+  return t == F64 ? reinterpret_cast<const double*>(p)[i] : (double)reinterpret_cast<const float*>(p)[i];
+}
+
+// One record per blockIdx.y, output elements strided over blockIdx.x.
+__global__ void kron_kernel(const KronRec* __restrict__ recs) {
+  const KronRec& R = recs[blockIdx.y];
+  const int64_t QJ = (int64_t)R.Q * R.J, RL = (int64_t)R.R * R.L;
+  const int64_t n = (int64_t)R.P * R.I * QJ * RL;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % RL, b = (e / RL) % QJ, a = e / (RL * QJ);
+    const int64_t p = a / R.I, i = a % R.I, q = b / R.J, j = b % R.J, r = c / R.L, l = c % R.L;
+    const double v = ld_any(R.H, R.tH, (p * R.Q + q) * R.R + r) * ld_any(R.B, R.tB, (i * R.J + j) * R.L + l);
+    if (R.tF == F64) reinterpret_cast<double*>(R.F)[e] = v;
+    else reinterpret_cast<float*>(R.F)[e] = (float)v;
   }
 }
 
@@ -268,6 +288,16 @@ hipError_t launch_root_norm(const StateRec* r, int n, hipStream_t s) {
 hipError_t launch_phi_scale(const PhiRec* r, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(phi_scale_kernel, dim3(n), dim3(NT), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0) return hipSuccess;
+  const int bx = (int)std::min<int64_t>((max_elems + 255) / 256, 4096);
+  for (int i0 = 0; i0 < n; i0 += kMaxY) {
+    const int ny = std::min(kMaxY, n - i0);
+    hipLaunchKernelGGL(kron_kernel, dim3(bx, ny), dim3(256), 0, s, r + i0);
+  }
   return hipGetLastError();
 }
 

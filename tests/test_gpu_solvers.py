@@ -1,0 +1,208 @@
+"""Operator application (Lemma (operator)) and the truncated solvers of
+Section 5 (Algorithms (CG) and (richardson)) on the GPU, through the C ABI,
+against the oracle's implementation of the same steps.
+
+Operators: Kronecker sums sum_mu I (x) .. (x) M_mu (x) .. (x) I with SPD M_mu
+(a synthetic SPD H-operator of hierarchical rank 2), and a random dense
+H-operator of rank 3 for the application alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ht_oracle as O
+from oracle import operators as OP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1708_03340_amd as H
+    H.lib()
+    return H
+
+
+def rand_ht(rng, d, n, ranks, rows=None):
+    tr = O.Tree(d)
+    U, B = [None] * d, {}
+    for t in range(tr.n_nodes):
+        if tr.is_leaf(t):
+            mu = tr.mode(t)
+            U[mu] = rng.standard_normal(((rows or n)[mu], ranks[t]))
+        else:
+            s1, s2 = tr.sons[t]
+            B[t] = rng.standard_normal((ranks[s1], ranks[s2]) if t == 0 else (ranks[t], ranks[s1], ranks[s2]))
+    return O.HT(tr, U, B, 0)
+
+
+def dev(H, X):
+    import torch
+    return H.DeviceHT.from_arrays(X.d, X.U, [X.B.get(t) for t in range(X.tree.n_nodes)], X.log2_scale,
+                                  frame_dtype=torch.float64, transfer_dtype=torch.float64)
+
+
+def to_oracle(D):
+    U, B, s = D.to_host()
+    return O.HT(O.Tree(D.d), U, B, s)
+
+
+def spd_mats(rng, d, n, lo=1.0, hi=3.0):
+    out = []
+    for m in n:
+        q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        out.append((q * rng.uniform(lo, hi, size=m)[None, :]) @ q.T / d)
+    return out
+
+
+@pytest.mark.parametrize("kind", ["kron_sum", "dense_rank3"])
+def test_apply_matches_oracle(H, kind):
+    say(f"case ht_apply {kind}")
+    rng = np.random.default_rng(31 if kind == "kron_sum" else 32)
+    d = 6
+    n = [int(v) for v in rng.integers(3, 12, size=d)]
+    if kind == "kron_sum":
+        L = OP.kron_sum_operator([rng.standard_normal((m, m)) for m in n])
+    else:
+        L = rand_ht(rng, d, n, [1] + [3] * (2 * d - 2), rows=[m * m for m in n])
+    A = rand_ht(rng, d, n, [1] + [4] * (2 * d - 2))
+    A.log2_scale = 5
+    C = H.ht_apply(dev(H, L), dev(H, A))
+    ref = OP.apply(L, A)
+    err = O.rel_diff(to_oracle(C), ref)
+    say(f"  rel err vs oracle {err:.3e}, ranks {C.ranks[:3]}")
+    assert C.ranks[1:] == ref.ranks()[1:]
+    assert err <= 1e-13
+
+
+def test_apply_then_truncate(H):
+    """C = L A (rank 2 x 16 = 32) truncated to rank 12 on the GPU against the
+    oracle's truncation of its own L A."""
+    import torch
+    say("case ht_apply then ht_truncate")
+    rng = np.random.default_rng(33)
+    d, n = 8, [20] * 8
+    L = OP.kron_sum_operator(spd_mats(rng, d, n))
+    A = rand_ht(rng, d, n, [1] + [16] * (2 * d - 2))
+    C = H.ht_apply(dev(H, L), dev(H, A))
+    tr = H.Truncator([C], [1.0], mode=H.HT_RANK_FIXED, ranks=[12] * (2 * d - 1), precision=H.HT_PREC_FP64,
+                     out_frame_dtype=torch.float64, out_transfer_dtype=torch.float64)
+    res = tr()
+    torch.cuda.synchronize()
+    T, _ = O.truncate(OP.apply(L, A), mode="fixed", ranks=[12] * (2 * d - 1))
+    err = O.rel_diff(to_oracle(res.out), T)
+    say(f"  rel err vs oracle {err:.3e}")
+    assert err <= 1e-10
+
+
+def system(rng, d, n):
+    mats = spd_mats(rng, d, n)
+    Aop = OP.kron_sum_operator(mats)
+    B = rand_ht(rng, d, n, [1] + [2] * (2 * d - 2))
+    return Aop, B
+
+
+def perturbed(B):
+    """B with one leaf-frame entry moved by a few ulps: the oracle's own
+    sensitivity to rounding, against which the GPU iterates are measured."""
+    P = B.copy()
+    P.U[0] = P.U[0].copy()
+    P.U[0][1, 0] *= 1.0 + 4.0 * np.finfo(float).eps
+    return P
+
+
+# Each step truncates sums of nearly parallel iterates (X_j and D_j, R_j and
+# Z share most of their frames: the stacked frames of such a sum have
+# singular values down to 1e-11 and below), which any backward-stable path
+# resolves only to the sensitivity of the truncation to its Gramians: on
+# such sums met in these runs, Gramians perturbed by K u (the backward error
+# of an eigensolver at K = 12) move the oracle's result by up to 2.5e-10,
+# and a shifted CholeskyQR2 in place of its Householder QR by 7e-12.  A
+# whole run is held to twice the first figure, or to 100 times the oracle's
+# own drift where a cut inside the spectrum amplifies rounding from step to
+# step.
+STEP_TOL = 5e-10
+
+
+def test_cg_iterates_match_oracle(H):
+    """Algorithm (CG) with T = fixed rank 6 from the same input on both
+    sides: the GPU iterates follow the oracle's step by step.  n = 16 exceeds
+    every rank that reaches a truncation (2 x 6 after the operator, 6 + 6 in
+    the sums), so the frames are of full column rank; rank-deficient frames
+    have a test of their own."""
+    from paper_1708_03340_amd import solvers as SV
+    say("case CG iterates, d=4 n=16, fixed rank 6")
+    rng = np.random.default_rng(34)
+    d, n = 4, [16] * 4
+    Aop, B = system(rng, d, n)
+    hg, ho, hp = [], [], []
+    T = OP.truncation("fixed", ranks=[6] * 7)
+    SV.cg(dev(H, Aop), dev(H, B), SV.Trunc("fixed", rank=6), eps=0.0, max_steps=6, history=hg)
+    OP.cg(Aop, B, T, eps=0.0, max_steps=6, history=ho)
+    OP.cg(Aop, perturbed(B), T, eps=0.0, max_steps=6, history=hp)
+    assert len(hg) == len(ho) == 6
+    for j, (g, o, p) in enumerate(zip(hg, ho, hp)):
+        e = O.rel_diff(to_oracle(g["X"]), o["X"])
+        drift = O.rel_diff(p["X"], o["X"])
+        ea = abs(g["alpha"] - o["alpha"]) / abs(o["alpha"])
+        say(f"  step {j}: X rel err {e:.3e} (oracle's own drift {drift:.3e}), alpha rel err {ea:.2e}, "
+            f"<R,R> {g['rr']:.6e} vs {o['rr']:.6e}")
+        assert e <= max(STEP_TOL, 100 * drift)
+        assert ea <= max(STEP_TOL, 100 * drift)
+
+
+def test_cg_solves_spd_system(H):
+    """With T = relative accuracy 1e-8, GPU CG stopped at a residual of
+    1e-8 ||B|| reaches the solution of the full linear system
+    (numpy.linalg.solve) to kappa (1 + steps) 1e-8: kappa <= 3 for this
+    operator (spectrum in [1, 3]), and every step adds at most one
+    truncation error to the recursively updated residual.  (The tolerance
+    rule reads the tail from Gramian eigenvalues, sigma^2, so in float64 it
+    resolves accuracies down to about 1e-8, not 1e-12.)"""
+    from paper_1708_03340_amd import solvers as SV
+    say("case CG convergence, d=4 n=6, T to 1e-8")
+    rng = np.random.default_rng(35)
+    d, n = 4, [6] * 4
+    Aop, B = system(rng, d, n)
+    x = np.linalg.solve(OP.operator_matrix(Aop, n), O.full(B).reshape(-1))
+    X, steps = SV.cg(dev(H, Aop), dev(H, B), SV.Trunc("tol", eps=1e-8), eps=1e-8 * np.sqrt(O.inner(B, B)),
+                     max_steps=100)
+    err = np.linalg.norm(O.full(to_oracle(X)).reshape(-1) - x) / np.linalg.norm(x)
+    say(f"  {steps} steps, error vs the exact solution {err:.3e}, ranks {X.ranks}")
+    assert steps < 100
+    assert err <= 3.0 * (1 + steps) * 1e-8
+
+
+def test_richardson_iterates_match_oracle(H):
+    """Algorithm (richardson) with omega = 2 / (lambda_min + lambda_max) and
+    T = fixed rank 6 from the same input on both sides, held to the gate of
+    the CG test (n = 16 for frames of full column rank).  The spectrum of a
+    Kronecker sum is the set of sums of one eigenvalue of each M_mu, so its
+    extremes are the sums of the extremes."""
+    from paper_1708_03340_amd import solvers as SV
+    say("case Richardson iterates, d=4 n=16, fixed rank 6")
+    rng = np.random.default_rng(36)
+    d, n = 4, [16] * 4
+    mats = spd_mats(rng, d, n)
+    Aop = OP.kron_sum_operator(mats)
+    B = rand_ht(rng, d, n, [1] + [2] * (2 * d - 2))
+    ev = [np.linalg.eigvalsh(M) for M in mats]
+    omega = 2.0 / (sum(e[0] for e in ev) + sum(e[-1] for e in ev))
+    T = OP.truncation("fixed", ranks=[6] * 7)
+    gA, gB = dev(H, Aop), dev(H, B)
+    X, Xo, Xp = gB, B, perturbed(B)
+    for j in range(8):
+        X = SV.richardson_step(gA, X, gB, omega, SV.Trunc("fixed", rank=6))
+        Xo = OP.richardson_step(Aop, Xo, B, omega, T)
+        Xp = OP.richardson_step(Aop, Xp, B, omega, T)
+        e, drift = O.rel_diff(to_oracle(X), Xo), O.rel_diff(Xp, Xo)
+        say(f"  step {j}: rel err vs oracle {e:.3e} (oracle's own drift {drift:.3e})")
+        assert e <= max(STEP_TOL, 100 * drift)

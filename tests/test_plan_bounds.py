@@ -24,7 +24,9 @@ def L():
                                                      P(H.HtTruncOpts), P(ctypes.c_int32)]
     L.ht_debug_validate_inner.argtypes = [P(H.HtDesc), P(H.HtDesc)]
     L.ht_debug_validate_norm.argtypes = [P(H.HtDesc), ctypes.c_int32]
-    for f in ("truncate", "orthogonalize", "gramians", "entries", "truncate_batched", "inner", "norm"):
+    L.ht_debug_validate_apply.argtypes = [P(H.HtDesc), P(H.HtDesc)]
+    for f in ("truncate", "orthogonalize", "gramians", "entries", "truncate_batched", "inner", "norm",
+              "apply"):
         getattr(L, "ht_debug_validate_" + f).restype = ctypes.c_int
     return L
 
@@ -130,6 +132,15 @@ def test_inner_plans_in_bounds(L, d, n, kx, ky, fx, fy):
 def test_norm_plans_in_bounds(L, d, n, k, n_in):
     X = (H.HtDesc * n_in)(*[desc(d, n, uniform(d, k)) for _ in range(n_in)])
     check(L, L.ht_debug_validate_norm(X, n_in))
+
+
+@pytest.mark.parametrize("d,n,kl,ka,fl,fa", [(2, 3, 2, 3, 0, 0), (4, 16, 2, 32, 0, 1), (7, 9, 3, 5, 1, 0),
+                                            (16, 64, 2, 64, 1, 1), (64, 400, 2, 64, 0, 1)])
+def test_apply_plans_in_bounds(L, d, n, kl, ka, fl, fa):
+    """ht_apply (Lemma (operator)): operator frames of n^2 rows."""
+    Lop = desc(d, n * n, uniform(d, kl), fl)
+    A = desc(d, n, uniform(d, ka), fa)
+    check(L, L.ht_debug_validate_apply(ctypes.byref(Lop), ctypes.byref(A)))
 
 
 def test_validator_catches_overrun(L):
