@@ -21,10 +21,13 @@ same workload on the host cores.  `graph_ms_per_step` replays the headline step 
 `inner_product` times <A, C> by Definition (phi) and the
 difference norm ||A - C|| on the same inputs.  `large_single` times the large single
 workload (d = 128, n = 1e5, k = 64 per summand, truncated to rank 64) and
-ht_entries of its result at 1e6 random multi-indices.
+ht_entries of its result at 1e6 random multi-indices.  `operator_apply`
+times ht_apply (Lemma (operator)) at d = 64, n = 400, ranks 20, and `cg`
+the steps of truncated CG (Algorithm (CG)) at d = 64, n = 1000.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -275,6 +278,82 @@ def inner_products(H, torch, A, C, a, c, steps=20, with_cpu=True):
     return out
 
 
+def operator_apply(H, torch, steps=5):
+    """Lemma (operator) at the paper's operator workload: d = 64, n = 400,
+    tensor and operator ranks 20 (the product has ranks 400), N(0,1) float32
+    frames and transfer tensors drawn on the device, output preallocated.
+    The Kronecker kernel writes every product transfer tensor (400^3 float32
+    per inner node) and is bound by HBM writes."""
+    d, n, k = 64, 400, 20
+    nn = 2 * d - 1
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(400)
+    L = device_tensor(H, torch, d, n * n, k, None, gen)
+    A = device_tensor(H, torch, d, n, k, None, gen)
+    C = H.DeviceHT.empty(d, [n] * d, [1] + [k * k] * (nn - 1), torch.float32, torch.float32)
+    H.ht_apply(L, A, C)
+    t = timed(lambda: H.ht_apply(L, A, C), steps, torch)
+    H.profile_enable(True)
+    H.profile_reset()
+    H.ht_apply(L, A, C)
+    torch.cuda.synchronize()
+    prof = H.profile_read()
+    H.profile_enable(False)
+    H.profile_reset()
+    kron = [e for e in prof if e["kernel"].startswith("kron_kernel")]
+    kms = sum(e["ms"] for e in kron)
+    kbytes = sum(e["bytes"] for e in kron)
+    out = dict(workload="H-operator application (Lemma (operator)) d=64 n=400, operator and tensor ranks 20 "
+                        "(product ranks 400), float32",
+               ms_per_apply=t * 1e3, value=1.0 / t, unit="operator applications/s", steps=steps,
+               kron_ms=kms, kron_alg_bytes=kbytes,
+               kron_roofline=dict(bound="hbm", achieved=kbytes / (kms * 1e-3) / 1e9 if kms else None,
+                                  peak=HBM_PEAK / 1e9, unit="GB/s",
+                                  frac=kbytes / (kms * 1e-3) / HBM_PEAK if kms else None))
+    log(f"bench: operator application {t * 1e3:.3f} ms; Kronecker kernel {kms:.3f} ms, "
+        f"{kbytes / max(kms * 1e-3, 1e-12) / 1e9:.0f} GB/s")
+    del L, A, C
+    torch.cuda.empty_cache()
+    return out
+
+
+def cg_solver(H, torch, steps=4):
+    """Algorithm (CG) in HT arithmetic on the device: d = 64, n = 1000, the
+    Kronecker-sum operator of M_mu = Q diag(U[1, 3]) Q^T / d (SPD, spectrum
+    in [1, 3]), a right-hand side of ranks 8 (N(0,1) float64), T = fixed rank
+    32 (float64 path).  One CG step is an operator application, four
+    truncations of sums of rank 64 and two inner products; the figure is
+    (time of `steps` steps - time of the start alone) / steps."""
+    from paper_1708_03340_amd import solvers as SV
+    d, n, kb = 64, 1000, 8
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1000)
+    mats = []
+    for _ in range(d):
+        q, _ = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=gen))
+        lam = 1.0 + 2.0 * torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+        mats.append((q * lam[None, :]) @ q.T / d)
+    Aop = SV.kron_sum_operator(mats)
+    B = device_tensor(H, torch, d, n, kb, None, gen)
+    B = H.DeviceHT(d, B.n, B.ranks, [u.double() for u in B.leaves],
+                   [b.double() if b is not None else None for b in B.transfer], 0)
+    T = SV.Trunc("fixed", rank=32)
+    SV.cg(Aop, B, T, eps=0.0, max_steps=1)
+    t0 = timed(lambda: SV.cg(Aop, B, T, eps=0.0, max_steps=0), 2, torch)
+    hist = []
+    tn = timed(lambda: SV.cg(Aop, B, T, eps=0.0, max_steps=steps, history=hist), 1, torch)
+    per = (tn - t0) / steps
+    out = dict(workload="truncated CG (Algorithm (CG)) d=64 n=1000, Kronecker-sum SPD operator, right-hand side "
+                        "ranks 8, T = fixed rank 32 (float64)",
+               ms_per_cg_step=per * 1e3, value=1.0 / per, unit="CG steps/s", steps=steps,
+               residual_log2_norms=[0.5 * h["rr_log2"] for h in hist])
+    log(f"bench: CG {per * 1e3:.2f} ms per step; log2 of the residual norms "
+        + " ".join(f"{r:.1f}" for r in out["residual_log2_norms"]))
+    del Aop, B, mats
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +530,8 @@ def main():
     out["inner_product"] = inner_products(H, torch, A, C, a, c, with_cpu=not args.no_cpu)
     out["batched"] = None if args.no_large else batched(H, torch)
     out["large_single"] = None if args.no_large else large_single(H, torch)
+    out["operator_apply"] = None if args.no_large else operator_apply(H, torch)
+    out["cg"] = cg_solver(H, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline (one sum-truncation)")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -401,8 +401,14 @@ void add_kron(Plan& P, const std::vector<KronRec>& r) {
   Op op;
   op.kind = OP_KRON;
   op.count = (int)r.size();
-  for (const auto& k : r)
-    op.c[0] = std::max<int64_t>(op.c[0], (int64_t)k.P * k.Q * k.R * k.I * k.J * k.L);
+  for (const auto& k : r) {
+    const double nF = (double)k.P * k.Q * k.R * k.I * k.J * k.L;
+    op.c[0] = std::max<int64_t>(op.c[0], (int64_t)nF);
+    // one product per element of F; compulsory traffic: H and B read once, F written once
+    op.flops += nF;
+    op.bytes_alg += (double)k.P * k.Q * k.R * esize(k.tH) + (double)k.I * k.J * k.L * esize(k.tB) +
+                    nF * esize(k.tF);
+  }
   op.toff = put(P, r);
   op.label = g_label;
   op.stream = g_stream;

@@ -112,21 +112,22 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   for (int p = 0; p < NB; ++p) {
     double* D = &L[16 * p * LDL + 16 * p];
     // ---- diagonal block, by wave 0 in registers: lane r (mod 16) holds row r
-    // of the block and row r of the elimination matrix E (E A = U, unit lower
-    // triangular).  Pivot j and row j reach every lane by readlane; the rank-1
-    // updates are register FMAs.  Then R_pp = D^{-1/2} U and, from E U^T = D,
-    // X_pp = R_pp^{-1} = E^T D^{-1/2} (D: the pivots).  A block with a dropped
-    // pivot gets its inverse by back substitution instead (unit rows there).
+    // of the block, made exactly symmetric from its upper triangle.  Step j
+    // takes pivot j by readlane, forms row j of R_pp, R_j = a_j / sqrt(p_j),
+    // and applies the symmetric rank-1 update a_rc -= R_j[r] R_j[c] to every
+    // entry, the lower ones included, so that the block stays bitwise
+    // symmetric: lane r's own a_rj serves as R_j[r] (times 1/sqrt(p_j)).  A
+    // Gaussian elimination that takes its multipliers from the lower entries
+    // while the rows come from the upper ones lets the two drift apart, and a
+    // run of tiny pivots (rank-deficient frames) amplifies that drift into a
+    // wrong Schur complement.  X_pp = R_pp^{-1} follows by back substitution.
     if (wave == 0) {
       const int r = l16;
-      double ar[16], er[16];
+      double ar[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        ar[c] = D[r * LDL + c];
-        er[c] = c == r ? 1.0 : 0.0;
-      }
+      for (int c = 0; c < 16; ++c) ar[c] = c >= r ? D[r * LDL + c] : D[c * LDL + r];
       double rs = 1.0;
-      bool blockdrop = false, mydrop = false;
+      bool mydrop = false;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int g = 16 * p + j;
@@ -140,33 +141,25 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
           dropped[g] = drop ? 1 : 0;
           if (drop) any = 1;
         }
-        // branch-free: a dropped pivot eliminates nothing (multiplier 0), so
-        // the updates stay in place whatever the pivot
-        blockdrop = blockdrop || drop;
+        // branch-free: a dropped pivot updates nothing (factor 0)
         mydrop = mydrop || (drop && r == j);
         const double pv = drop ? 1.0 : pj;
-        const double ip = rcp_nr(pv);
+        const double rj = rsqrt_nr(pv);
         if (r == j) {
-          rs = rsqrt_nr(pv);
-          ar[j] = pv;   // U_jj is the (possibly clamped) pivot
+          rs = rj;
+          ar[j] = pv;   // the (possibly clamped) pivot: R_jj = pv / sqrt(pv)
         }
-        const double m = (r > j && !drop) ? ar[j] * ip : 0.0;
+        const double mr = (r > j && !drop) ? ar[j] * rj : 0.0;   // R_j[r]
 #pragma unroll
-        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-m, lane_val(ar[c], j), ar[c]);
-#pragma unroll
-        for (int c = 0; c <= j; ++c) er[c] = fma(-m, lane_val(er[c], j), er[c]);
+        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-mr, lane_val(ar[c], j) * rj, ar[c]);
       }
       if (lane < 16) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) D[r * LDL + c] = (c >= r && !mydrop) ? ar[c] * rs : 0.0;
-        if (!blockdrop) {
-          // column r of X_pp: X[i][r] = E[r][i] / sqrt(d_r)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) Xd[p][i * LDD + r] = i <= r ? er[i] * rs : 0.0;
-        }
       }
-      // X_pp = R_pp^{-1} (unit diagonal on dropped rows), lanes 0..15 one column each
-      if (blockdrop && lane < 16) {
+      // X_pp = R_pp^{-1} (unit diagonal on dropped rows), lanes 0..15 one
+      // column each; the lanes read R_pp as this wave wrote it above
+      if (lane < 16) {
         const int c = lane;
         double x[16];
 #pragma unroll

@@ -14,8 +14,8 @@
 //     merge of two blocks with eigen-decompositions Q_j D_j Q_j^T solves the
 //     rank-one update D + rho z z^T, z = Q^T v / sqrt(2) (rho doubled):
 //       - the eigenvalues are sorted; entries with rho |z_j| below
-//         2 u max|D| of the block, and pairs of poles closer than that after a
-//         plane rotation of their z entries, deflate (a wave per merge at
+//         2 u max(max|D| of the block, u), and pairs of poles closer than that
+//         after a plane rotation of their z entries, deflate (a wave per merge at
 //         the top four depths, else a thread, runs the scan and rotates the
 //         two eigenvector columns);
 //       - each remaining root of 1 + rho sum_j z_j^2 / (d_j - lambda) = 0 is
@@ -188,6 +188,26 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
         const int r = ty + 16 * i, c = tx + 16 * q;
         A[i][q] = (r < K && c < K) ? gld(&a.Bh[r * K + c]) : 0.0;
       }
+    // max |A|: a column below the diagonal with norm under u^2 max|A| is
+    // taken as zero (no reflection).  Its square may leave the float64
+    // range, and alpha (alpha - x0) with it, which would make tau infinite;
+    // the entries it drops are below the deflation floor of step 2.
+    double thr;
+    {
+      double m = 0.0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) m = fmax(m, fabs(A[i][q]));
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      if (lane == 0) part[wave] = m;
+      __syncthreads();
+      double amax = part[0];
+      for (int w = 1; w < NT / 64; ++w) amax = fmax(amax, part[w]);
+      const double fl = kUnit * kUnit * amax;
+      thr = fl * fl;
+      __syncthreads();   // part is reused below
+    }
     for (int k = 0; k + 2 < K; ++k) {
       const int kb = k >> 4;
       // publish column k below the diagonal, and the diagonal entry
@@ -210,7 +230,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
       if (KT > 64) hi = xs[min(lane + 64, KT - 1)] * (lane + 64 < KT ? 1.0 : 0.0);
       const double nrm2 = wave_sum(xs[lane] * xs[lane] + hi * hi);
       double tau = 0.0, alpha = x0;
-      if (nrm2 > 0.0) {
+      if (nrm2 > thr && nrm2 > 0.0) {
         alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
         tau = 1.0 / (alpha * (alpha - x0));
       }
@@ -352,7 +372,11 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           if (!(blo < bmid && bmid < bhi)) continue;
           const int bm = bhi - blo;
           const double brho = 2.0 * fabs(eo[bmid - 1]);
-          const double tol = 2.0 * kUnit * fmax(fabs(ds[blo]), fabs(ds[bhi - 1]));
+          // block-relative, with an absolute floor of 2 u^2 (T has max-norm 1):
+          // eigenvalues below u^2 are far under the float64 resolution of the
+          // Gramian, and poles or weights at those scales make the secular
+          // equation and the eigenvector entries z_j / (d_j - lambda) overflow
+          const double tol = 2.0 * kUnit * fmax(fmax(fabs(ds[blo]), fabs(ds[bhi - 1])), kUnit);
           int nk = 0, pk = -1;
           for (int p = 0; p < bm; ++p) {
             const int P = blo + p;

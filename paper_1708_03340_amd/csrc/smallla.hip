@@ -202,17 +202,30 @@ __device__ __forceinline__ double ld_any(const void* p, int t, int64_t i) {
   return t == F64 ? reinterpret_cast<const double*>(p)[i] : (double)reinterpret_cast<const float*>(p)[i];
 }
 
-// One record per blockIdx.y, output elements strided over blockIdx.x.
-__global__ void kron_kernel(const KronRec* __restrict__ recs) {
+// F = H (x) B, F[(p,i), (q,j), (r,l)] = H[p,q,r] B[i,j,l] with the H index
+// slowest in every mode.  One record per blockIdx.y; each wave writes whole
+// rows (p,i,q,j) of R*L contiguous elements, rows strided over the waves of
+// the grid, so the index decode of a row is wave-uniform (scalar) and the
+// per-element work is one 32-bit split of c into (r, l), two loads and a
+// coalesced store.
+__global__ __launch_bounds__(256) void kron_kernel(const KronRec* __restrict__ recs) {
   const KronRec& R = recs[blockIdx.y];
-  const int64_t QJ = (int64_t)R.Q * R.J, RL = (int64_t)R.R * R.L;
-  const int64_t n = (int64_t)R.P * R.I * QJ * RL;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e % RL, b = (e / RL) % QJ, a = e / (RL * QJ);
-    const int64_t p = a / R.I, i = a % R.I, q = b / R.J, j = b % R.J, r = c / R.L, l = c % R.L;
-    const double v = ld_any(R.H, R.tH, (p * R.Q + q) * R.R + r) * ld_any(R.B, R.tB, (i * R.J + j) * R.L + l);
-    if (R.tF == F64) reinterpret_cast<double*>(R.F)[e] = v;
-    else reinterpret_cast<float*>(R.F)[e] = (float)v;
+  const int64_t QJ = (int64_t)R.Q * R.J;
+  const int RL = R.R * R.L;
+  const int64_t rows = (int64_t)R.P * R.I * QJ;
+  const int lane = threadIdx.x & 63;
+  const int64_t ws = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; row < rows; row += ws) {
+    const int64_t a = row / QJ, b = row - a * QJ;
+    const int64_t p = a / R.I, i = a - p * R.I, q = b / R.J, j = b - q * R.J;
+    const int64_t hb = (p * R.Q + q) * R.R, bb = (i * R.J + j) * R.L, fb = row * RL;
+    for (int c = lane; c < RL; c += 64) {
+      const int r = c / R.L, l = c - r * R.L;
+      const double v = ld_any(R.H, R.tH, hb + r) * ld_any(R.B, R.tB, bb + l);
+      if (R.tF == F64) reinterpret_cast<double*>(R.F)[fb + c] = v;
+      else reinterpret_cast<float*>(R.F)[fb + c] = (float)v;
+    }
   }
 }
 
