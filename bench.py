@@ -361,7 +361,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-large", action="store_true", help="skip the large single workload (d=128, n=1e5)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large single workload (d=128, n=1e5), the batch and the operator application")
+    ap.add_argument("--no-cg", action="store_true", help="skip the truncated-CG figure")
     ap.add_argument("--breakdown", action="store_true", help="print the per-step profile to stderr")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the benchmark, run three plain device copies of MIB MiB (a known "
@@ -531,7 +533,7 @@ def main():
     out["batched"] = None if args.no_large else batched(H, torch)
     out["large_single"] = None if args.no_large else large_single(H, torch)
     out["operator_apply"] = None if args.no_large else operator_apply(H, torch)
-    out["cg"] = cg_solver(H, torch)
+    out["cg"] = None if args.no_cg else cg_solver(H, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline (one sum-truncation)")
         out["cpu_baseline"] = cpu_baseline(cfg)

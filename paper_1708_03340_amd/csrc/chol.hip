@@ -153,30 +153,32 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 #pragma unroll
         for (int c = j + 1; c < 16; ++c) ar[c] = fma(-mr, lane_val(ar[c], j) * rj, ar[c]);
       }
+      // row r of R_pp (a zero row where the pivot was dropped) and 1 / R_rr
+      // (1 on a dropped row, whose row of the inverse is a unit row)
+      double rrow[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) rrow[c] = (c >= r && !mydrop) ? ar[c] * rs : 0.0;
+      const double rinv = mydrop ? 1.0 : rs;   // R_rr = pv / sqrt(pv), so 1 / R_rr = rs
       if (lane < 16) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) D[r * LDL + c] = (c >= r && !mydrop) ? ar[c] * rs : 0.0;
+        for (int c = 0; c < 16; ++c) D[r * LDL + c] = rrow[c];
       }
-      // X_pp = R_pp^{-1} (unit diagonal on dropped rows), lanes 0..15 one
-      // column each; the lanes read R_pp as this wave wrote it above
-      if (lane < 16) {
-        const int c = lane;
+      // X_pp = R_pp^{-1} by back substitution in registers: lane c (< 16)
+      // forms column c, the entries of R coming from their rows' lanes
+      {
+        const int c = l16;
         double x[16];
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
-          if (i > c) {
-            x[i] = 0.0;
-          } else {
-            const bool di = dropped[16 * p + i] != 0;
-            double s = i == c ? 1.0 : 0.0;
+          double sum = i == c ? 1.0 : 0.0;
 #pragma unroll
-            for (int k = i + 1; k < 16; ++k)
-              if (k <= c) s -= D[i * LDL + k] * x[k];
-            x[i] = s * rcp_nr(di ? 1.0 : D[i * LDL + i]);
-          }
+          for (int k = i + 1; k < 16; ++k) sum = fma(-lane_val(rrow[k], i), x[k], sum);
+          x[i] = sum * lane_val(rinv, i);
         }
+        if (lane < 16) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Xd[p][i * LDD + c] = x[i];
+          for (int i = 0; i < 16; ++i) Xd[p][i * LDD + c] = x[i];
+        }
       }
     }
     __syncthreads();
