@@ -136,6 +136,9 @@ size_t put(Plan& P, const std::vector<T>& v) {
 
 int esize(int t) { return t == F32 ? 4 : 8; }
 
+// algorithmic flops of one eigensolve with vectors, per K^3 (see add_small)
+constexpr double kEigFlopsPerK3 = 4.0 / 3.0 + 4.0 / 3.0 + 2.0;
+
 
 GemmDesc blank_desc() {
   GemmDesc d;
@@ -316,10 +319,11 @@ void add_small(Plan& P, int kind, const std::vector<SmallArgs>& a) {
     op.bytes_alg += 2.0 * 8.0 * x.K * x.K;
     const double k3 = (double)x.K * x.K * x.K;
     // operation counts: symmetric eigensolver with vectors (Householder
-    // tridiagonalisation 4/3 K^3, implicit QL with vectors about 6 K^3,
-    // back-transformation 2 K^3); Cholesky K^3/3 and triangular inverse K^3/3,
-    // and in the second step the two triangular products, K^3/3 each
-    if (kind == OP_EIG) op.flops += (4.0 / 3.0 + 8.0) * k3;
+    // tridiagonalisation 4/3 K^3, the divide-and-conquer eigenvector products
+    // about 4/3 K^3, back-transformation 2 K^3); Cholesky K^3/3 and triangular
+    // inverse K^3/3, and in the second step the two triangular products,
+    // K^3/3 each
+    if (kind == OP_EIG) op.flops += kEigFlopsPerK3 * k3;
     if (kind == OP_CHOL1 || kind == OP_CHOL2) op.flops += 2.0 / 3.0 * k3;
     if (kind == OP_CHOL2) op.flops += 2.0 / 3.0 * k3;
   }
@@ -596,7 +600,7 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
             for (const auto& x : *part) {
               e.i0 = std::max(e.i0, (int)x.K);
               e.bytes_alg += 2.0 * 8.0 * x.K * x.K;
-              e.flops += (4.0 / 3.0 + 8.0) * (double)x.K * x.K * x.K;
+              e.flops += kEigFlopsPerK3 * (double)x.K * x.K * x.K;
             }
             M.ops.push_back(e);
           }
