@@ -171,6 +171,7 @@ def batched(H, torch, steps=3):
     bt = H.BatchTruncator(problems)
     bt()
     t = timed(bt, steps, torch)
+    t_graph = graph_replay(H, torch, bt, steps)
     H.profile_enable(True)
     H.profile_reset()
     bt()
@@ -185,6 +186,7 @@ def batched(H, torch, steps=3):
     out = dict(workload="256 HT sums in one ht_truncate_batched call: d ~ U{4..32}, n ~ U[100,4096], "
                         "k ~ U{8..48} per summand, each truncated to its own k (mixed precision)",
                ms_per_batch=t * 1e3, value=256.0 / t, unit="sum-truncations/s", steps=steps,
+               graph_ms_per_batch=t_graph * 1e3,
                launches_per_batch=launches, alg_flops=flops, achieved_tflops=flops / t / 1e12,
                frac_fp64_peak=flops / t / PEAKS["double"])
     del problems, bt
@@ -193,7 +195,8 @@ def batched(H, torch, steps=3):
 
 
 def graph_replay(H, torch, tr, steps):
-    """The same d=64 sum-truncation captured once in a HIP graph and replayed."""
+    """The same call (a Truncator or BatchTruncator) captured once in a HIP
+    graph and replayed."""
     tr()
     torch.cuda.synchronize()
     s = torch.cuda.Stream()

@@ -90,3 +90,63 @@ def test_truncate_graph_replays(H):
         assert e_eager <= max(1e-13, 10 * spread) and e_or <= 1e-10
         other()
         torch.cuda.synchronize()
+
+
+def test_batched_truncate_graph_replays(H):
+    """ht_truncate_batched over 10 uneven problems (d 4..9, n 50..300, ranks
+    4..16 per summand, float64 path, fixed and tolerance rank rules),
+    captured once in a HIP graph and replayed three times with eager work
+    between the replays: every problem of every replay matches the eager
+    batch (ten times the spread of two eager runs, at least 1e-13) and the
+    oracle (1e-10)."""
+    import torch
+    say("case graph capture of ht_truncate_batched, 10 uneven problems")
+    rng = np.random.default_rng(5151)
+    f64 = torch.float64
+    problems, refs = [], []
+    for b in range(10):
+        d, n, k = int(rng.integers(4, 10)), int(rng.integers(50, 301)), int(rng.integers(4, 17))
+        A, C = rand_ht(rng, d, n, k), rand_ht(rng, d, n, k)
+        nn = 2 * d - 1
+        devs = [H.DeviceHT.from_arrays(d, X.U, [X.B.get(t) for t in range(nn)], 0, frame_dtype=f64,
+                                       transfer_dtype=f64) for X in (A, C)]
+        if b % 2 == 0:
+            r = max(2, k - 2)
+            problems.append(dict(Xs=devs, coef=[1.0, 0.5], mode=H.HT_RANK_FIXED, ranks=[r] * nn,
+                                 precision=H.HT_PREC_FP64, out_frame_dtype=f64, out_transfer_dtype=f64))
+            refs.append(O.truncate(O.add(A, C, 1.0, 0.5), mode="fixed", ranks=[r] * nn)[0])
+        else:
+            problems.append(dict(Xs=devs, coef=[1.0, 0.5], mode=H.HT_RANK_TOL, eps=1e-3, relative=True,
+                                 precision=H.HT_PREC_FP64, out_frame_dtype=f64, out_transfer_dtype=f64))
+            refs.append(O.truncate(O.add(A, C, 1.0, 0.5), mode="tol", eps=1e-3)[0])
+    bt = H.BatchTruncator(problems)
+    eager = [to_oracle(r.out) for r in bt()]
+    torch.cuda.synchronize()
+    again = [to_oracle(r.out) for r in bt()]
+    spread = max(O.rel_diff(x, y) for x, y in zip(again, eager))
+    worst = max(O.rel_diff(x, y) for x, y in zip(eager, refs))
+    say(f"  eager vs oracle worst {worst:.3e}; two eager runs differ by {spread:.3e}")
+    assert worst <= 1e-10
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        bt(stream=s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            bt(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in bt.outs:
+            for u in o.leaves:
+                u.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        got = [to_oracle(o) for o in bt.outs]
+        e_eager = max(O.rel_diff(x, y) for x, y in zip(got, eager))
+        e_or = max(O.rel_diff(x, y) for x, y in zip(got, refs))
+        say(f"  replay {rep}: vs eager {e_eager:.3e}, vs oracle {e_or:.3e}")
+        assert e_eager <= max(1e-13, 10 * spread) and e_or <= 1e-10
+        bt()
+        torch.cuda.synchronize()
