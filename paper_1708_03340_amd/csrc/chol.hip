@@ -113,7 +113,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
     double* D = &L[16 * p * LDL + 16 * p];
     // ---- diagonal block, by wave 0 in registers: lane r (mod 16) holds row r
     // of the block, made exactly symmetric from its upper triangle.  Step j
-    // takes pivot j by readlane, forms row j of R_pp, R_j = a_j / sqrt(p_j),
+    // takes pivot j by a DPP row broadcast, forms row j of R_pp, R_j = a_j / sqrt(p_j),
     // and applies the symmetric rank-1 update a_rc -= R_j[r] R_j[c] to every
     // entry, the lower ones included, so that the block stays bitwise
     // symmetric: lane r's own a_rj serves as R_j[r] (times 1/sqrt(p_j)).  A
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int g = 16 * p + j;
-        double pj = lane_val(ar[j], j);
+        double pj = row16_bcast(ar[j], j);
         bool drop = false;
         if (g >= K) pj = 1.0;   // padding
         else if (!(pj > tol)) {
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         }
         const double mr = (r > j && !drop) ? ar[j] * rj : 0.0;   // R_j[r]
 #pragma unroll
-        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-mr, lane_val(ar[c], j) * rj, ar[c]);
+        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-mr, row16_bcast(ar[c], j) * rj, ar[c]);
       }
       // row r of R_pp (a zero row where the pivot was dropped) and 1 / R_rr
       // (1 on a dropped row, whose row of the inverse is a unit row)
@@ -172,8 +172,8 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         for (int i = 15; i >= 0; --i) {
           double sum = i == c ? 1.0 : 0.0;
 #pragma unroll
-          for (int k = i + 1; k < 16; ++k) sum = fma(-lane_val(rrow[k], i), x[k], sum);
-          x[i] = sum * lane_val(rinv, i);
+          for (int k = i + 1; k < 16; ++k) sum = fma(-row16_bcast(rrow[k], i), x[k], sum);
+          x[i] = sum * row16_bcast(rinv, i);
         }
         if (lane < 16) {
 #pragma unroll

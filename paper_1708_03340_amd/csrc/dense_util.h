@@ -64,6 +64,29 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Lane j's value (j a compile-time constant after unrolling) to every lane of
+// its 16-lane DPP row: row_newbcast, a VALU move with no scalar round trip.
+__device__ __forceinline__ double row16_bcast(double v, int j) {
+  switch (j & 15) {
+    case 0: return dpp_f64<0x150>(v);
+    case 1: return dpp_f64<0x151>(v);
+    case 2: return dpp_f64<0x152>(v);
+    case 3: return dpp_f64<0x153>(v);
+    case 4: return dpp_f64<0x154>(v);
+    case 5: return dpp_f64<0x155>(v);
+    case 6: return dpp_f64<0x156>(v);
+    case 7: return dpp_f64<0x157>(v);
+    case 8: return dpp_f64<0x158>(v);
+    case 9: return dpp_f64<0x159>(v);
+    case 10: return dpp_f64<0x15A>(v);
+    case 11: return dpp_f64<0x15B>(v);
+    case 12: return dpp_f64<0x15C>(v);
+    case 13: return dpp_f64<0x15D>(v);
+    case 14: return dpp_f64<0x15E>(v);
+    default: return dpp_f64<0x15F>(v);
+  }
+}
+
 // Sum over the 16 lanes of a DPP row, returned to every lane of the row:
 // swap neighbours, swap pairs (quad permutations), then the half-row and
 // row mirrors join quads into eights and eights into sixteen.
