@@ -181,8 +181,12 @@ def _metadata(lines):
 # The split-K Gram instances with float64 rows (four per-wave copies of the
 # chunk loop in 256 registers) spill two 64-bit values: 8 registers, at most
 # 32 bytes of scratch, one store and one reload of each per chunk in one of
-# the four copies.  Every other kernel spills nothing.
+# the four copies.  The Cholesky kernel (its diagonal-block step holds a row,
+# the DPP broadcasts of the pivot row and the inverse's column in registers)
+# moves 4 registers into accumulation registers, with no scratch memory.
+# Every other kernel spills nothing.
 SPILL_ALLOWED = re.compile(r"gemm_rk_kernelId[df]dLi1ELi32ELb0ELb0E")
+SPILL_TO_ACC = re.compile(r"chol_kernel")
 
 
 def test_no_spills_scratch_or_lds_overflow(asm):
@@ -193,6 +197,10 @@ def test_no_spills_scratch_or_lds_overflow(asm):
             if SPILL_ALLOWED.search(name):
                 assert md.get("vgpr_spill_count", 0) <= 8, f"{src} {name}: VGPR spills"
                 assert md.get("private_segment_fixed_size", 0) <= 32, f"{src} {name}: scratch memory"
+                continue
+            if SPILL_TO_ACC.search(name):
+                assert md.get("vgpr_spill_count", 0) <= 4, f"{src} {name}: VGPR spills"
+                assert md.get("private_segment_fixed_size", 0) == 0, f"{src} {name}: scratch memory"
                 continue
             assert md.get("vgpr_spill_count", 0) == 0, f"{src} {name}: VGPR spills"
             assert md.get("private_segment_fixed_size", 0) == 0, f"{src} {name}: scratch memory"
