@@ -62,8 +62,13 @@ __device__ __forceinline__ double dc_quad(double c, double b1, double b2, double
   return low ? y : -y;
 }
 
-// Sum over the two lanes of a pair (2x, 2x+1).
-__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, 1, 64); }
+// The other lane of a pair (2x, 2x+1), by DPP quad_perm [1,0,3,2] (a VALU
+// move; both lanes of the pair are active wherever these are used).
+__device__ __forceinline__ double pair_other(double v) { return dpp_f64<0xB1>(v); }
+__device__ __forceinline__ int pair_other(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+
+// Sum over the two lanes of a pair.
+__device__ __forceinline__ double pair_sum(double v) { return v + pair_other(v); }
 
 // Root i of the secular equation 1 + rho sum_j z_j^2 / (d_j - lambda) = 0
 // for poles d[0] < ... < d[nk-1] (the root lies in (d_i, d_i+1), the last
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           const double w = dg[y];
           r += (w < v || (w == v && y < x)) ? 1 : 0;
         }
-        r += __shfl_xor(r, 1, 64);
+        r += pair_other(r);
         r = min(r, m - 1);
         if (h == 0) {
           const double sgn = eo[mid - 1] >= 0.0 ? 1.0 : -1.0;
@@ -463,7 +468,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
             const double lq = (d[orgs[lo + q]] - dj) + taus[lo + q];   // lambda_q - d_j
             w *= lq * rcp_nr(d[q] - dj);
           }
-          w *= __shfl_xor(w, 1, 64);
+          w *= pair_other(w);
           if (h == 0) zh[x] = copysign(sqrt(fmax(w, 0.0)), zs[x]);
         }
         const double v = nv[x];
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(NT, KT <= 96 ? 2 : 1) void eig_kernel(const SmallAr
           const double u = nv[y];
           r += (u < v || (u == v && y < x)) ? 1 : 0;
         }
-        r += __shfl_xor(r, 1, 64);
+        r += pair_other(r);
         if (h == 0) newcol[x] = (unsigned char)min(r, m - 1);
       }
       __syncthreads();
