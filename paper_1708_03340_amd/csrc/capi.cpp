@@ -408,6 +408,7 @@ void add_kron(Plan& P, const std::vector<KronRec>& r) {
   for (const auto& k : r) {
     const double nF = (double)k.P * k.Q * k.R * k.I * k.J * k.L;
     op.c[0] = std::max<int64_t>(op.c[0], (int64_t)nF);
+    op.c[1] = std::max<int64_t>(op.c[1], (int64_t)k.P * k.I);   // mode-1 index pairs (p, i)
     // one product per element of F; compulsory traffic: H and B read once, F written once
     op.flops += nF;
     op.bytes_alg += (double)k.P * k.Q * k.R * esize(k.tH) + (double)k.I * k.J * k.L * esize(k.tB) +
@@ -871,7 +872,7 @@ ht_status launch_plan(ht_context* ctx, const Plan& P, void* dtable, hipStream_t 
         e = launch_phi_scale(reinterpret_cast<const PhiRec*>(tb + op.toff), op.count, stream);
         break;
       case OP_KRON:
-        e = launch_kron(reinterpret_cast<const KronRec*>(tb + op.toff), op.count, op.c[0], stream);
+        e = launch_kron(reinterpret_cast<const KronRec*>(tb + op.toff), op.count, op.c[0], op.c[1], stream);
         break;
     }
     if (e != hipSuccess) return fail(HT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -3085,7 +3086,8 @@ ht_status validate_plan(const Plan& P, int64_t m_entries) {
         const KronRec& r = kr[i];
         const std::string w = tag + " kron record " + std::to_string(i);
         const int64_t nh = (int64_t)r.P * r.Q * r.R, nb = (int64_t)r.I * r.J * r.L;
-        if (nh < 1 || nb < 1 || nh * nb > op.c[0]) return fail(HT_EINVAL, "validator: kron size " + w);
+        if (nh < 1 || nb < 1 || nh * nb > op.c[0] || (int64_t)r.P * r.I > op.c[1])
+          return fail(HT_EINVAL, "validator: kron size " + w);
         if ((s = check_range(r.H, 0, nh - 1, esize(r.tH), w + " H")) ||
             (s = check_range(r.B, 0, nb - 1, esize(r.tB), w + " B")) ||
             (s = check_range(r.F, 0, nh * nb - 1, esize(r.tF), w + " F")))

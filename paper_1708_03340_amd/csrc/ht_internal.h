@@ -227,7 +227,7 @@ struct KronRec {
   int32_t P, Q, R, I, J, L;
   int32_t pad;
 };
-hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, hipStream_t s);
+hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, int64_t max_a, hipStream_t s);
 
 hipError_t launch_fill(const FillRec* r, int n, size_t max_bytes, hipStream_t s);
 hipError_t launch_set_state(const StateRec* r, int n, hipStream_t s);

@@ -203,28 +203,36 @@ __device__ __forceinline__ double ld_any(const void* p, int t, int64_t i) {
 }
 
 // F = H (x) B, F[(p,i), (q,j), (r,l)] = H[p,q,r] B[i,j,l] with the H index
-// slowest in every mode.  One record per blockIdx.y; each wave writes whole
-// rows (p,i,q,j) of R*L contiguous elements, rows strided over the waves of
-// the grid, so the index decode of a row is wave-uniform (scalar) and the
-// per-element work is one 32-bit split of c into (r, l), two loads and a
-// coalesced store.
+// slowest in every mode.  One record per blockIdx.y; a workgroup takes one
+// mode-1 index a = (p,i) at a time, its waves the rows b = (q,j) in turn
+// (the pair advanced by additions, no division per row), and the lanes of a
+// wave R*L contiguous elements of a row, split into (r, l) by a float
+// reciprocal with an exact integer correction (c < 2^24).
 __global__ __launch_bounds__(256) void kron_kernel(const KronRec* __restrict__ recs) {
   const KronRec& R = recs[blockIdx.y];
-  const int64_t QJ = (int64_t)R.Q * R.J;
-  const int RL = R.R * R.L;
-  const int64_t rows = (int64_t)R.P * R.I * QJ;
+  const int I = R.I, J = R.J, L = R.L, Q = R.Q, RR = R.R;
+  const int QJ = Q * J, RL = RR * L;
+  const int nA = R.P * I;
   const int lane = threadIdx.x & 63;
-  const int64_t ws = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; row < rows; row += ws) {
-    const int64_t a = row / QJ, b = row - a * QJ;
-    const int64_t p = a / R.I, i = a - p * R.I, q = b / R.J, j = b - q * R.J;
-    const int64_t hb = (p * R.Q + q) * R.R, bb = (i * R.J + j) * R.L, fb = row * RL;
-    for (int c = lane; c < RL; c += 64) {
-      const int r = c / R.L, l = c - r * R.L;
-      const double v = ld_any(R.H, R.tH, hb + r) * ld_any(R.B, R.tB, bb + l);
-      if (R.tF == F64) reinterpret_cast<double*>(R.F)[fb + c] = v;
-      else reinterpret_cast<float*>(R.F)[fb + c] = (float)v;
+  const int nw = blockDim.x >> 6;
+  const float invL = 1.0f / (float)L;
+  for (int a = blockIdx.x; a < nA; a += gridDim.x) {
+    const int p = a / I, i = a - p * I;
+    int q = wave / J, j = wave - q * J;
+    for (int b = wave; b < QJ; b += nw) {
+      const int64_t hb = ((int64_t)p * Q + q) * RR, bb = ((int64_t)i * J + j) * L;
+      const int64_t fb = ((int64_t)a * QJ + b) * RL;
+      for (int c = lane; c < RL; c += 64) {
+        int r = (int)((float)c * invL);
+        int l = c - r * L;
+        if (l < 0) { --r; l += L; } else if (l >= L) { ++r; l -= L; }
+        const double v = ld_any(R.H, R.tH, hb + r) * ld_any(R.B, R.tB, bb + l);
+        if (R.tF == F64) reinterpret_cast<double*>(R.F)[fb + c] = v;
+        else reinterpret_cast<float*>(R.F)[fb + c] = (float)v;
+      }
+      j += nw;
+      while (j >= J) { j -= J; ++q; }
     }
   }
 }
@@ -304,9 +312,9 @@ hipError_t launch_phi_scale(const PhiRec* r, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, hipStream_t s) {
-  if (n <= 0 || max_elems <= 0) return hipSuccess;
-  const int bx = (int)std::min<int64_t>((max_elems + 255) / 256, 4096);
+hipError_t launch_kron(const KronRec* r, int n, int64_t max_elems, int64_t max_a, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0 || max_a <= 0) return hipSuccess;
+  const int bx = (int)std::min<int64_t>(max_a, 4096);   // one mode-1 index (p, i) per workgroup
   for (int i0 = 0; i0 < n; i0 += kMaxY) {
     const int ny = std::min(kMaxY, n - i0);
     hipLaunchKernelGGL(kron_kernel, dim3(bx, ny), dim3(256), 0, s, r + i0);
