@@ -83,6 +83,57 @@ def test_apply_matches_oracle(H, kind):
     assert err <= 1e-13
 
 
+def test_apply_float32_output_and_unequal_ranks(H):
+    """Lemma (operator) with float32 frames and transfer tensors for the
+    tensor, a float64 operator of uneven ranks, and a float32 result:
+    relative error within the float32 rounding of the result (1e-6)."""
+    import torch
+    say("case ht_apply float32 result, uneven ranks")
+    rng = np.random.default_rng(39)
+    d = 5
+    n = [int(v) for v in rng.integers(3, 10, size=d)]
+    tr = O.Tree(d)
+    rl = [1] + [int(v) for v in rng.integers(1, 4, size=2 * d - 2)]
+    ra = [1] + [int(v) for v in rng.integers(2, 6, size=2 * d - 2)]
+    L = rand_ht(rng, d, n, rl, rows=[m * m for m in n])
+    A = rand_ht(rng, d, n, ra)
+    dL = dev(H, L)
+    dA = H.DeviceHT.from_arrays(d, A.U, [A.B.get(t) for t in range(tr.n_nodes)], 0,
+                                frame_dtype=torch.float32, transfer_dtype=torch.float32)
+    C = H.ht_apply(dL, dA, frame_dtype=torch.float32, transfer_dtype=torch.float32)
+    assert C.leaves[0].dtype == torch.float32
+    Af = O.HT(tr, [u.astype(np.float32).astype(np.float64) for u in A.U],
+              {t: b if t == 0 else b.astype(np.float32).astype(np.float64) for t, b in A.B.items()}, 0)
+    err = O.rel_diff(to_oracle(C), OP.apply(L, Af))
+    say(f"  rel err vs oracle {err:.3e}, ranks {C.ranks[:4]}")
+    assert C.ranks[1:] == [a * b for a, b in zip(rl[1:], ra[1:])]
+    assert err <= 1e-6
+
+
+def test_richardson_reaches_the_exact_solution(H):
+    """Algorithm (richardson) on the GPU with T to relative accuracy 1e-9 and
+    omega = 2 / (lambda_min + lambda_max): after 60 steps the iterate is
+    within max(1e-7, 10 rate^60) of numpy.linalg.solve's solution, rate =
+    (kappa - 1) / (kappa + 1) (the truncation adds at most its accuracy per
+    step, summed geometrically: 1e-9 / (1 - rate))."""
+    from paper_1708_03340_amd import solvers as SV
+    say("case Richardson convergence, d=4 n=5")
+    rng = np.random.default_rng(40)
+    d, n = 4, [5] * 4
+    mats = spd_mats(rng, d, n, 1.0, 2.0)
+    Aop = OP.kron_sum_operator(mats)
+    B = rand_ht(rng, d, n, [1] + [2] * (2 * d - 2))
+    Lm = OP.operator_matrix(Aop, n)
+    ev = np.linalg.eigvalsh(Lm)
+    omega = 2.0 / (ev[0] + ev[-1])
+    rate = (ev[-1] - ev[0]) / (ev[-1] + ev[0])
+    x = np.linalg.solve(Lm, O.full(B).reshape(-1))
+    X = SV.richardson(dev(H, Aop), dev(H, B), dev(H, B), omega, SV.Trunc("tol", eps=1e-9), steps=60)
+    err = np.linalg.norm(O.full(to_oracle(X)).reshape(-1) - x) / np.linalg.norm(x)
+    say(f"  60 steps: error vs the exact solution {err:.3e} (rate {rate:.3f}), ranks {X.ranks}")
+    assert err <= max(1e-7, 10 * rate ** 60)
+
+
 def test_kron_sum_operator_on_device(H):
     """The device builder of Kronecker-sum operators lays the operator out
     exactly as the oracle's."""
