@@ -518,7 +518,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic (seeded; float32 N(0,1) leaf frames, transfer tensors with singular values 0.9^i)",
-        "config": {"workload": "HT sum truncation d=64 n=10000 k=64+64 -> rel tol 1e-6 (mixed precision)",
+        "config": {"workload": "HT sum truncation d=64 n=10000 k=64+64 -> rel tol 1e-6 (mixed path: float32 inputs "
+                               "and outputs; at this shape every product runs in float64, see speedup_mixed_vs_fp64)",
                    "d": 64, "n": 10000, "k": 64, "sum_rank": 128, "eps": cfg["eps"], "rank_rule": "tolerance",
                    "parallelism": "single GPU"},
         "fp64_value": 1.0 / t_fp64 if t_fp64 else None,
