@@ -367,6 +367,9 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large single workload (d=128, n=1e5), the batch and the operator application")
     ap.add_argument("--no-cg", action="store_true", help="skip the truncated-CG figure")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline steps: no graph replay, inner products, batch, large, operator or CG "
+                         "figures (for counter runs that divide by the number of steps)")
     ap.add_argument("--breakdown", action="store_true", help="print the per-step profile to stderr")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the benchmark, run three plain device copies of MIB MiB (a known "
@@ -532,12 +535,13 @@ def main():
         "roofline": roof,
         "roofline_mfma": roof_mfma,
     }
-    out["graph_ms_per_step"] = graph_replay(H, torch, mixed, args.steps) * 1e3
-    out["inner_product"] = inner_products(H, torch, A, C, a, c, with_cpu=not args.no_cpu)
-    out["batched"] = None if args.no_large else batched(H, torch)
-    out["large_single"] = None if args.no_large else large_single(H, torch)
-    out["operator_apply"] = None if args.no_large else operator_apply(H, torch)
-    out["cg"] = None if args.no_cg else cg_solver(H, torch)
+    ex = not args.no_extras
+    out["graph_ms_per_step"] = graph_replay(H, torch, mixed, args.steps) * 1e3 if ex else None
+    out["inner_product"] = inner_products(H, torch, A, C, a, c, with_cpu=not args.no_cpu) if ex else None
+    out["batched"] = None if (args.no_large or not ex) else batched(H, torch)
+    out["large_single"] = None if (args.no_large or not ex) else large_single(H, torch)
+    out["operator_apply"] = None if (args.no_large or not ex) else operator_apply(H, torch)
+    out["cg"] = None if (args.no_cg or not ex) else cg_solver(H, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline (one sum-truncation)")
         out["cpu_baseline"] = cpu_baseline(cfg)
