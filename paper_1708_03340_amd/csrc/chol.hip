@@ -12,8 +12,8 @@
 //    as those of the sum A + A) and flags them.
 //
 // Right-looking blocked factorisation, blocks of 16.  For each block column
-// p: wave 0 factors the diagonal block in LDS (one pivot at a time) and
-// inverts its factor; the block row R_pq = R_pp^{-T} A_pq and the symmetric
+// p: wave 0 factors the diagonal block in registers (left-looking, one
+// pivot at a time) and inverts its factor; the block row R_pq = R_pp^{-T} A_pq and the symmetric
 // trailing update A_qr -= R_pq^T R_pr are float64 MFMA 16x16x4 products
 // spread over the four waves.  R^{-1} is then formed by blocked back
 // substitution, X_pq = -X_pp sum_{k=p+1..q} R_pk X_kq, also on MFMA.  A
@@ -111,69 +111,61 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 
   for (int p = 0; p < NB; ++p) {
     double* D = &L[16 * p * LDL + 16 * p];
-    // ---- diagonal block, by wave 0 in registers: lane r (mod 16) holds row r
-    // of the block, made exactly symmetric from its upper triangle.  Step j
-    // takes pivot j by a DPP row broadcast, forms row j of R_pp, R_j = a_j / sqrt(p_j),
-    // and applies the symmetric rank-1 update a_rc -= R_j[r] R_j[c] to every
-    // entry, the lower ones included, so that the block stays bitwise
-    // symmetric: lane r's own a_rj serves as R_j[r] (times 1/sqrt(p_j)).  A
-    // Gaussian elimination that takes its multipliers from the lower entries
-    // while the rows come from the upper ones lets the two drift apart, and a
-    // run of tiny pivots (rank-deficient frames) amplifies that drift into a
-    // wrong Schur complement.  X_pp = R_pp^{-1} follows by back substitution.
+    // ---- diagonal block, by wave 0 in registers, left-looking: lane r
+    // (mod 16) owns column r of the block, A_jr for j <= r taken from the
+    // upper triangle (the only one the trailing updates keep), and builds
+    // column r of R_pp.  Step j forms lane r's entry of column j of the
+    // Schur complement, s_r = A_jr - sum_{i<j} R_ir R_ij (R_ij from lane j
+    // by a DPP row broadcast), takes the pivot s_j from lane j and sets
+    // R_jr = s_r / sqrt(s_j).  Every entry is formed once, so no symmetric
+    // copy can drift, and the pivot chain waits only on the last term of
+    // each sum.  X_pp = R_pp^{-1} follows by column-oriented back
+    // substitution.
     if (wave == 0) {
       const int r = l16;
-      double ar[16];
+      double rc[16];      // rc[j] = R_jr (0 below the diagonal)
+      double s[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) ar[c] = c >= r ? D[r * LDL + c] : D[c * LDL + r];
-      double rs = 1.0;
-      bool mydrop = false;
+      for (int j = 0; j < 16; ++j) s[j] = j <= r ? D[j * LDL + r] : 0.0;
+      double rinv = 1.0;  // 1 / R_rr; 1 on a dropped row (a unit row of the inverse)
+      unsigned dmask = 0;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int g = 16 * p + j;
-        double pj = row16_bcast(ar[j], j);
-        bool drop = false;
-        if (g >= K) pj = 1.0;   // padding
-        else if (!(pj > tol)) {
-          if (sweep == 1) pj = tol; else drop = true;
-        }
-        if (lane == 0) {
-          dropped[g] = drop ? 1 : 0;
-          if (drop) any = 1;
-        }
-        // branch-free: a dropped pivot updates nothing (factor 0)
-        mydrop = mydrop || (drop && r == j);
-        const double pv = drop ? 1.0 : pj;
+        double sj = s[j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) sj = fma(-rc[i], row16_bcast(rc[i], j), sj);
+        const double pj = row16_bcast(sj, j);
+        // branch-free pivot rule: padding takes 1; a pivot not above tol is
+        // clamped to tol in sweep 1 and dropped in sweep 2 (a zero row of R
+        // that updates nothing)
+        const bool pad = 16 * p + j >= K;
+        const bool small = !(pj > tol);
+        const bool drop = !pad && small && sweep != 1;
+        const double pv = pad ? 1.0 : (small ? (sweep == 1 ? tol : 1.0) : pj);
+        dmask |= drop ? (1u << j) : 0u;
         const double rj = rsqrt_nr(pv);
-        if (r == j) {
-          rs = rj;
-          ar[j] = pv;   // the (possibly clamped) pivot: R_jj = pv / sqrt(pv)
-        }
-        const double mr = (r > j && !drop) ? ar[j] * rj : 0.0;   // R_j[r]
-#pragma unroll
-        for (int c = j + 1; c < 16; ++c) ar[c] = fma(-mr, row16_bcast(ar[c], j) * rj, ar[c]);
+        const double v = r > j ? sj * rj : (r == j ? pv * rj : 0.0);
+        rc[j] = drop ? 0.0 : v;
+        if (r == j) rinv = drop ? 1.0 : rj;
       }
-      // row r of R_pp (a zero row where the pivot was dropped) and 1 / R_rr
-      // (1 on a dropped row, whose row of the inverse is a unit row)
-      double rrow[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) rrow[c] = (c >= r && !mydrop) ? ar[c] * rs : 0.0;
-      const double rinv = mydrop ? 1.0 : rs;   // R_rr = pv / sqrt(pv), so 1 / R_rr = rs
       if (lane < 16) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) D[r * LDL + c] = rrow[c];
+        for (int i = 0; i < 16; ++i) D[i * LDL + r] = rc[i];
+        dropped[16 * p + r] = (dmask >> r) & 1u;
+        if (lane == 0 && dmask) any = 1;
       }
-      // X_pp = R_pp^{-1} by back substitution in registers: lane c (< 16)
-      // forms column c, the entries of R coming from their rows' lanes
+      // X_pp: lane c forms column c, x = e_c, then for k = 15 .. 0:
+      // x_k /= R_kk, x_i -= R_ik x_k (i < k), R_ik from lane k
       {
         const int c = l16;
         double x[16];
 #pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          double sum = i == c ? 1.0 : 0.0;
+        for (int i = 0; i < 16; ++i) x[i] = i == c ? 1.0 : 0.0;
 #pragma unroll
-          for (int k = i + 1; k < 16; ++k) sum = fma(-row16_bcast(rrow[k], i), x[k], sum);
-          x[i] = sum * row16_bcast(rinv, i);
+        for (int k = 15; k >= 0; --k) {
+          x[k] *= row16_bcast(rinv, k);
+#pragma unroll
+          for (int i = 0; i < k; ++i) x[i] = fma(-row16_bcast(rc[i], k), x[k], x[i]);
         }
         if (lane < 16) {
 #pragma unroll

@@ -56,12 +56,13 @@ __device__ __forceinline__ double lane_val(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// DPP move of a double within rows of 16 lanes (CTRL: a DPP control code).
+// DPP move of a double within rows of 16 lanes (CTRL: a DPP control code
+// whose source lane always lies in the row, so every lane is written and
+// bound_ctrl changes nothing).  With bound_ctrl set the compiler needs no
+// initialised destination, and row_newbcast becomes one v_mov_b64_dpp.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
+  return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, true);
 }
 
 // Lane j's value (j a compile-time constant after unrolling) to every lane of

@@ -65,7 +65,7 @@ __device__ __forceinline__ double dc_quad(double c, double b1, double b2, double
 // The other lane of a pair (2x, 2x+1), by DPP quad_perm [1,0,3,2] (a VALU
 // move; both lanes of the pair are active wherever these are used).
 __device__ __forceinline__ double pair_other(double v) { return dpp_f64<0xB1>(v); }
-__device__ __forceinline__ int pair_other(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int pair_other(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true); }
 
 // Sum over the two lanes of a pair.
 __device__ __forceinline__ double pair_sum(double v) { return v + pair_other(v); }
