@@ -57,12 +57,12 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const int l16 = lane & 15, l4 = lane >> 4;
   const double* Gin = sweep == 1 ? a.G : a.G2;
   bool bad = false;
-  // wave w loads rows w, w + 4, ...; lane c columns c and c + 64; eight rows
-  // in flight per wave
-  for (int r0 = wave; r0 < Kp; r0 += 32) {
-    double v[8][2];
+  // wave w loads rows w, w + 4, ...; lane c columns c and c + 64; sixteen
+  // rows in flight per wave
+  for (int r0 = wave; r0 < Kp; r0 += 64) {
+    double v[16][2];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         // every load is issued (clamped address, masked value): a guarded
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         v[u][h] = g * (in ? 1.0 : 0.0) + ((!in && r == c) ? 1.0 : 0.0);
       }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int r = r0 + 4 * u, c = lane + 64 * h;

@@ -95,13 +95,26 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
   double alpha = D.alpha;
   if (D.alpha_dev) alpha *= gld(D.alpha_dev);
 
+  // S into LDS: thread tid owns column tid % 128 and every (SB_NT / 128)-th
+  // row; all its loads are issued before the first store (clamped addresses,
+  // masked values: rows past Kt point at row Kt - 1), so the fill waits on
+  // one memory latency, not one per element
   auto load_S = [&](int b) {
     __syncthreads();   // previous users of Ss are done; the row tables are written
-    for (int idx = tid; idx < Kp * 128; idx += SB_NT) {
-      const int k = idx >> 7, m = idx & 127;
-      double v = 0.0;
-      if (k < Kt && m < Ms) v = ld_as_double<TS>(srow[k] + b * s_b + m * s_m);
-      Ss[k][m] = v;
+    constexpr int RS = SB_NT / 128, NU = 16;   // rows per thread and pass
+    const int m = tid & 127;
+    const int64_t moff = (int64_t)b * s_b + (int64_t)min(m, Ms - 1) * s_m;
+#pragma unroll 1
+    for (int k0 = tid >> 7; k0 < SB_K; k0 += RS * NU) {
+      double v[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int k = k0 + RS * u;
+        const double x = ld_as_double<TS>(srow[k] + moff);
+        v[u] = (k < Kt && m < Ms) ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) Ss[k0 + RS * u][m] = v[u];
     }
     __syncthreads();
   };
@@ -123,9 +136,9 @@ __global__ __launch_bounds__(512 / WN, 1) void gemm_sb_kernel(const GemmDesc* __
   if (it >= nitems) return;
   int cur_b = it / tilesN;
   __syncthreads();   // row tables visible
-  load_S(cur_b);
   double bc[KS][WN], bn[KS][WN];
-  load_T(it, 0, bc);
+  load_T(it, 0, bc);   // in flight during the fill of S
+  load_S(cur_b);
   while (true) {
     const int next = it + gridDim.x;
     doublex4 acc[NRB][WN];
@@ -240,13 +253,23 @@ __global__ __launch_bounds__(512, 1) void gemm_sb_ring_kernel(const GemmDesc* __
   if (it0 >= nitems) return;
   const int nq = (nitems - it0 + (int)gridDim.x - 1) / (int)gridDim.x;   // items of this workgroup
 
+  // S into LDS as in gemm_sb_kernel: all loads of a thread in flight at once
   auto load_S = [&](int b) {
     __syncthreads();
-    for (int idx = tid; idx < SB_K * 128; idx += NT) {
-      const int k = idx >> 7, m = idx & 127;
-      double v = 0.0;
-      if (k < Kt && m < Ms) v = ld_as_double<TS>(srow[k] + b * s_b + m * s_m);
-      Ss[k][m] = v;
+    constexpr int RS = NT / 128, NU = 16;   // rows per thread and pass
+    const int m = tid & 127;
+    const int64_t moff = (int64_t)b * s_b + (int64_t)min(m, Ms - 1) * s_m;
+#pragma unroll 1
+    for (int k0 = tid >> 7; k0 < SB_K; k0 += RS * NU) {
+      double v[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int k = k0 + RS * u;
+        const double x = ld_as_double<TS>(srow[k] + moff);
+        v[u] = (k < Kt && m < Ms) ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) Ss[k0 + RS * u][m] = v[u];
     }
     __syncthreads();
   };
@@ -266,11 +289,11 @@ __global__ __launch_bounds__(512, 1) void gemm_sb_ring_kernel(const GemmDesc* __
 
   int cur_b = it0 / tilesN;
   __syncthreads();   // row tables visible
-  load_S(cur_b);
   double B0[8], B1[8], B2[8], B3[8];
-  load_T(0, 0, B0);
+  load_T(0, 0, B0);   // the first three chunks are in flight during the fill of S
   load_T(0, 1, B1);
   load_T(0, 2, B2);
+  load_S(cur_b);
   doublex4 acc[8];
   auto chunk = [&](int c, const double (&bf)[8]) {
 #pragma unroll

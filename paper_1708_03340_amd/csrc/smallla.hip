@@ -82,24 +82,52 @@ __global__ void rank_kernel(const SmallArgs* __restrict__ all_args, const StateR
 }
 
 // Qm = Q[:, :rcap] with columns >= r zeroed (float64); QmT = Qm^T in the
-// forward-product type; optional sigma / ||A||.
+// forward-product type; optional sigma / ||A||.  Workgroup (node, y) takes
+// rows 16y .. 16y + 15 of Q: each thread issues its eight loads together
+// (clamped addresses, masked values), stores Qm row-major, and the slab is
+// transposed through LDS so that QmT is stored 16 contiguous entries at a
+// time.
 __global__ void proj_prep_kernel(const SmallArgs* __restrict__ args, const GlobalState* st) {
+  __shared__ double tile[16][KMAX + 1];
   const SmallArgs& a = args[blockIdx.x];
   if (a.st) st = a.st;
   const int K = a.K, rc = a.rcap;
   const int r = *a.rank_dev;
-  for (int idx = threadIdx.x; idx < K * rc; idx += blockDim.x) {
-    const int i = idx / rc, c = idx % rc;
-    const double v = c < r ? a.Q[i * K + c] : 0.0;
-    if (a.Qm) a.Qm[idx] = v;
+  const int i0 = 16 * blockIdx.y;
+  const int tid = threadIdx.x;
+  if (i0 < K && rc > 0) {
+    const int c = tid & 127, ty = tid >> 7;   // 256 threads: two rows per pass
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + ty + 2 * u;
+      const double x = a.Q[min(i, K - 1) * K + min(c, K - 1)];
+      v[u] = (i < K && c < rc && c < r) ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + ty + 2 * u;
+      if (a.Qm && i < K && c < rc) a.Qm[i * rc + c] = v[u];
+      tile[ty + 2 * u][c] = v[u];
+    }
+    __syncthreads();
     if (a.QmT) {
-      if (a.rf_type == F32) reinterpret_cast<float*>(a.QmT)[c * K + i] = (float)v;
-      else reinterpret_cast<double*>(a.QmT)[c * K + i] = v;
+      const int ii = tid & 15, c0 = tid >> 4;   // 16 columns per pass
+      const int i = i0 + ii;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const int cc = c0 + 16 * w;
+        if (cc < rc && i < K) {
+          const double x = tile[ii][cc];
+          if (a.rf_type == F32) reinterpret_cast<float*>(a.QmT)[cc * K + i] = (float)x;
+          else reinterpret_cast<double*>(a.QmT)[cc * K + i] = x;
+        }
+      }
     }
   }
-  if (a.sigma_out) {
+  if (a.sigma_out && blockIdx.y == 0) {
     const double n2 = st->norm2_units;
-    for (int i = threadIdx.x; i < KMAX; i += blockDim.x)
+    for (int i = tid; i < KMAX; i += blockDim.x)
       a.sigma_out[i] = (i < K && n2 > 0.0) ? sqrt(a.lam[i] / n2) : 0.0;
   }
 }
@@ -290,7 +318,7 @@ hipError_t launch_rank_select(const SmallArgs* args, const StateRec* r, int n, h
 
 hipError_t launch_proj_prep(const SmallArgs* args, int n, const GlobalState* st, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(proj_prep_kernel, dim3(n), dim3(256), 0, s, args, st);
+  hipLaunchKernelGGL(proj_prep_kernel, dim3(n, KMAX / 16), dim3(256), 0, s, args, st);
   return hipGetLastError();
 }
 
