@@ -256,88 +256,139 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   }
   if (any && tid == 0) atomicOr(&st->flags, 1u);
 
-  // ---- sweep 2: R = R2 R1 and Ri = R1^{-1} R2^{-1}.  Upper block (p, q),
-  // p <= q, numbered row by row, is formed by wave (number mod 4):
-  // R_pq = sum_{k=p..q} R2_pk R1_kq, Ri_pq = sum_{k=p..q} Ri1_pk X_kq.  The
-  // global operands of a block are loaded together (clamped addresses,
-  // masked values) before its products.
-  const int nblk = NB * (NB + 1) / 2;
-  constexpr int MAXJ = (KMAX / 16) * (KMAX / 16 + 1) / 2 / (NT / 64);   // blocks per wave
-  doublex4 racc[MAXJ];
+  // ---- sweep 2: R = R2 R1 and Ri = R1^{-1} R2^{-1} (products of block
+  // upper-triangular matrices).  Wave w takes the block columns w and
+  // NBMAX - 1 - w of R, R_pq = sum_{k=p..q} R2_pk R1_kq: it loads the whole
+  // column of R1 once (every load of a column in flight together), forms the
+  // column's blocks and stores them unnormalised.  Then it takes the block
+  // rows w and NBMAX - 1 - w of Ri, Ri_pq = sum_{k=p..q} Ri1_pk X_kq, from
+  // one load of the row of Ri1.  Finally every lane rescales the R entries
+  // it stored itself by 2^-e and writes Rf.
+  constexpr int NBMAX = KMAX / 16;
+  // the wave index in a scalar register (the loops below branch on it) and
+  // the node's pointers in locals (the stores would otherwise make the
+  // compiler reload them from the argument table)
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const double* const R1g = a.R1;
+  const double* const Ri1g = a.Ri1;
+  double* const Rg = a.R;
+  double* const Rig = a.Ri;
+  void* const Rfg = a.Rf;
+  const bool rf32 = a.rf_type == F32;
   double mx = 0.0;
+#pragma unroll 1
+  for (int u = 0; u < 2; ++u) {
+    const int q = u == 0 ? wv : NBMAX - 1 - wv;
+    if (q >= NB) continue;
+    double b1[NBMAX][4];   // R1_kq, B operand layout
 #pragma unroll
-  for (int j = 0; j < MAXJ; ++j) {
-    racc[j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    const int idx = wave + (NT / 64) * j;
-    if (idx >= nblk) continue;
-    int p = 0, rem = idx;
-    while (rem >= NB - p) {
-      rem -= NB - p;
-      ++p;
-    }
-    const int q = p + rem;
-    double b1[KMAX / 16][4], a1[KMAX / 16][4];
-#pragma unroll
-    for (int t = 0; t < KMAX / 16; ++t) {
-      if (p + t > q) break;
+    for (int k = 0; k < NBMAX; ++k)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int kr = 16 * (p + t) + 4 * s + l4;   // row of R1, column of Ri1
-        const int c = 16 * q + l16, r = 16 * p + l16;
-        const bool okb = kr < K && c < K, oka = r < K && kr < K;
-        b1[t][s] = gld(&a.R1[min(kr, K - 1) * K + min(c, K - 1)]) * (okb ? 1.0 : 0.0);
-        a1[t][s] = gld(&a.Ri1[min(r, K - 1) * K + min(kr, K - 1)]) * (oka ? 1.0 : 0.0);
+        const int kr = 16 * k + 4 * s + l4, c = 16 * q + l16;
+        const double x = gld(&R1g[min(kr, K - 1) * K + min(c, K - 1)]);
+        b1[k][s] = (k <= q && kr < K && c < K) ? x : 0.0;
       }
-    }
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0}, iacc = {0.0, 0.0, 0.0, 0.0};
+    doublex4 acc[NBMAX];
 #pragma unroll
-    for (int t = 0; t < KMAX / 16; ++t) {
-      const int k = p + t;
+    for (int p = 0; p < NBMAX; ++p) acc[p] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NBMAX; ++k) {
       if (k > q) break;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = 4 * s + l4;
-        const double r2 = L[(16 * p + l16) * LDL + 16 * k + kk] * ((k > p || kk >= l16) ? 1.0 : 0.0);
-        acc = mfma(r2, b1[t][s], acc);
-        const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
-        iacc = mfma(a1[t][s], xb, iacc);
+      for (int p = 0; p <= k; ++p)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kk = 4 * s + l4;
+          const double r2 = L[(16 * p + l16) * LDL + 16 * k + kk] * ((k > p || kk >= l16) ? 1.0 : 0.0);
+          acc[p] = mfma(r2, b1[k][s], acc[p]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NBMAX; ++p) {
+      if (p > q) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+        if (r < K && c < K) {
+          gst(&Rg[r * K + c], acc[p][v]);
+          mx = fmax(mx, fabs(acc[p][v]));
+        }
       }
     }
-    racc[j] = acc;
+  }
+#pragma unroll 1
+  for (int u = 0; u < 2; ++u) {
+    const int p = u == 0 ? wv : NBMAX - 1 - wv;
+    if (p >= NB) continue;
+    double a1[NBMAX][4];   // Ri1_pk, A operand layout
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
-      if (r < K && c < K) gst(&a.Ri[r * K + c], iacc[v]);
-      mx = fmax(mx, fabs(acc[v]));
+    for (int k = 0; k < NBMAX; ++k)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = 16 * p + l16, kc = 16 * k + 4 * s + l4;
+        const double x = gld(&Ri1g[min(r, K - 1) * K + min(kc, K - 1)]);
+        a1[k][s] = (k >= p && r < K && kc < K) ? x : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < NBMAX; ++q) {
+      if (q >= NB) break;
+      if (q < p) continue;
+      doublex4 iacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k <= q; ++k) {
+        if (k < p) continue;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kk = 4 * s + l4;
+          const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
+          iacc = mfma(a1[k][s], xb, iacc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+        if (r < K && c < K) gst(&Rig[r * K + c], iacc[v]);
+      }
     }
   }
   // blocks below the diagonal are zero
   for (int r = wave; r < K; r += NT / 64)
     for (int c = lane; c < (r & ~15); c += 64) {
-      gst(&a.R[r * K + c], 0.0);
-      gst(&a.Ri[r * K + c], 0.0);
-      if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[r * K + c] = 0.0f;
-      else reinterpret_cast<double*>(a.Rf)[r * K + c] = 0.0;
+      gst(&Rg[r * K + c], 0.0);
+      gst(&Rig[r * K + c], 0.0);
+      if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = 0.0f;
+      else reinterpret_cast<double*>(Rfg)[r * K + c] = 0.0;
     }
   const int e = exp2_of(wg_max(mx, red));
+  // rescale: each lane rescales the entries it stored above
+#pragma unroll 1
+  for (int u = 0; u < 2; ++u) {
+    const int q = u == 0 ? wv : NBMAX - 1 - wv;
+    if (q >= NB) continue;
+    double x[NBMAX][4];
 #pragma unroll
-  for (int j = 0; j < MAXJ; ++j) {
-    const int idx = wave + (NT / 64) * j;
-    if (idx >= nblk) continue;
-    int p = 0, rem = idx;
-    while (rem >= NB - p) {
-      rem -= NB - p;
-      ++p;
-    }
-    const int q = p + rem;
+    for (int p = 0; p < NBMAX; ++p)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
-      if (r < K && c < K) {
-        const double x = ldexp(racc[j][v], -e);
-        gst(&a.R[r * K + c], x);
-        if (a.rf_type == F32) reinterpret_cast<float*>(a.Rf)[r * K + c] = (float)x;
-        else reinterpret_cast<double*>(a.Rf)[r * K + c] = x;
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+        // clamped address, masked value: every load is issued (the barrier
+        // of the maximum above orders them after all stores of phase R)
+        const double y = gld(&Rg[min(r, K - 1) * K + min(c, K - 1)]);
+        x[p][v] = (p <= q && r < K && c < K) ? y : 0.0;
+      }
+#pragma unroll
+    for (int p = 0; p < NBMAX; ++p) {
+      if (p > q) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+        if (r < K && c < K) {
+          const double y = ldexp(x[p][v], -e);
+          gst(&Rg[r * K + c], y);
+          if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = (float)y;
+          else reinterpret_cast<double*>(Rfg)[r * K + c] = y;
+        }
       }
     }
   }
