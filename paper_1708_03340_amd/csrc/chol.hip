@@ -54,6 +54,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   const int K = a.K;
   const int NB = (K + 15) >> 4, Kp = NB * 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);   // the same, in a scalar register
   const int l16 = lane & 15, l4 = lane >> 4;
   const double* Gin = sweep == 1 ? a.G : a.G2;
   bool bad = false;
@@ -258,17 +259,16 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
 
   // ---- sweep 2: R = R2 R1 and Ri = R1^{-1} R2^{-1} (products of block
   // upper-triangular matrices).  Wave w takes the block columns w and
-  // NBMAX - 1 - w of R, R_pq = sum_{k=p..q} R2_pk R1_kq: it loads the whole
-  // column of R1 once (every load of a column in flight together), forms the
-  // column's blocks and stores them unnormalised.  Then it takes the block
-  // rows w and NBMAX - 1 - w of Ri, Ri_pq = sum_{k=p..q} Ri1_pk X_kq, from
-  // one load of the row of Ri1.  Finally every lane rescales the R entries
-  // it stored itself by 2^-e and writes Rf.
+  // NBMAX - 1 - w of R, R_pq = sum_{k=p..q} R2_pk R1_kq: it loads each column
+  // of R1 once (all loads of a column in flight together) and keeps the
+  // column's blocks in registers until the power-of-two normalisation is
+  // known.  Then it takes the block rows w and NBMAX - 1 - w of Ri,
+  // Ri_pq = sum_{k=p..q} Ri1_pk X_kq, from one load of the row of Ri1.  In
+  // both products the blocks of a row or column are advanced together for
+  // each k, so consecutive MFMAs feed different accumulators.
   constexpr int NBMAX = KMAX / 16;
-  // the wave index in a scalar register (the loops below branch on it) and
   // the node's pointers in locals (the stores would otherwise make the
   // compiler reload them from the argument table)
-  const int wv = __builtin_amdgcn_readfirstlane(wave);
   const double* const R1g = a.R1;
   const double* const Ri1g = a.Ri1;
   double* const Rg = a.R;
@@ -276,9 +276,12 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
   void* const Rfg = a.Rf;
   const bool rf32 = a.rf_type == F32;
   double mx = 0.0;
-#pragma unroll 1
+  doublex4 acc[2][NBMAX];
+#pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int q = u == 0 ? wv : NBMAX - 1 - wv;
+#pragma unroll
+    for (int p = 0; p < NBMAX; ++p) acc[u][p] = doublex4{0.0, 0.0, 0.0, 0.0};
     if (q >= NB) continue;
     double b1[NBMAX][4];   // R1_kq, B operand layout
 #pragma unroll
@@ -289,21 +292,32 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         const double x = gld(&R1g[min(kr, K - 1) * K + min(c, K - 1)]);
         b1[k][s] = (k <= q && kr < K && c < K) ? x : 0.0;
       }
-    doublex4 acc[NBMAX];
-#pragma unroll
-    for (int p = 0; p < NBMAX; ++p) acc[p] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < NBMAX; ++k) {
       if (k > q) break;
 #pragma unroll
-      for (int p = 0; p <= k; ++p)
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + l4;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kk = 4 * s + l4;
+        for (int p = 0; p <= k; ++p) {
           const double r2 = L[(16 * p + l16) * LDL + 16 * k + kk] * ((k > p || kk >= l16) ? 1.0 : 0.0);
-          acc[p] = mfma(r2, b1[k][s], acc[p]);
+          acc[u][p] = mfma(r2, b1[k][s], acc[u][p]);
         }
+      }
     }
+#pragma unroll
+    for (int p = 0; p < NBMAX; ++p)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
+        if (p <= q && r < K && c < K) mx = fmax(mx, fabs(acc[u][p][v]));
+      }
+  }
+  const int e = exp2_of(wg_max(mx, red));
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = u == 0 ? wv : NBMAX - 1 - wv;
+    if (q >= NB) continue;
 #pragma unroll
     for (int p = 0; p < NBMAX; ++p) {
       if (p > q) break;
@@ -311,12 +325,22 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
         if (r < K && c < K) {
-          gst(&Rg[r * K + c], acc[p][v]);
-          mx = fmax(mx, fabs(acc[p][v]));
+          const double y = ldexp(acc[u][p][v], -e);
+          gst(&Rg[r * K + c], y);
+          if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = (float)y;
+          else reinterpret_cast<double*>(Rfg)[r * K + c] = y;
         }
       }
     }
   }
+  // blocks below the diagonal are zero
+  for (int r = wave; r < K; r += NT / 64)
+    for (int c = lane; c < (r & ~15); c += 64) {
+      gst(&Rg[r * K + c], 0.0);
+      gst(&Rig[r * K + c], 0.0);
+      if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = 0.0f;
+      else reinterpret_cast<double*>(Rfg)[r * K + c] = 0.0;
+    }
 #pragma unroll 1
   for (int u = 0; u < 2; ++u) {
     const int p = u == 0 ? wv : NBMAX - 1 - wv;
@@ -330,65 +354,31 @@ __global__ __launch_bounds__(NT) void chol_kernel(const SmallArgs* __restrict__ 
         const double x = gld(&Ri1g[min(r, K - 1) * K + min(kc, K - 1)]);
         a1[k][s] = (k >= p && r < K && kc < K) ? x : 0.0;
       }
+    doublex4 iacc[NBMAX];
+#pragma unroll
+    for (int q = 0; q < NBMAX; ++q) iacc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NBMAX; ++k) {
+      if (k >= NB) break;
+      if (k < p) continue;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + l4;
+#pragma unroll
+        for (int q = k; q < NBMAX; ++q) {
+          const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
+          iacc[q] = mfma(a1[k][s], xb, iacc[q]);
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NBMAX; ++q) {
       if (q >= NB) break;
       if (q < p) continue;
-      doublex4 iacc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k <= q; ++k) {
-        if (k < p) continue;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kk = 4 * s + l4;
-          const double xb = k == q ? Xd[q][kk * LDD + l16] : L[(16 * q + l16) * LDL + 16 * k + kk];
-          iacc = mfma(a1[k][s], xb, iacc);
-        }
-      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
-        if (r < K && c < K) gst(&Rig[r * K + c], iacc[v]);
-      }
-    }
-  }
-  // blocks below the diagonal are zero
-  for (int r = wave; r < K; r += NT / 64)
-    for (int c = lane; c < (r & ~15); c += 64) {
-      gst(&Rg[r * K + c], 0.0);
-      gst(&Rig[r * K + c], 0.0);
-      if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = 0.0f;
-      else reinterpret_cast<double*>(Rfg)[r * K + c] = 0.0;
-    }
-  const int e = exp2_of(wg_max(mx, red));
-  // rescale: each lane rescales the entries it stored above
-#pragma unroll 1
-  for (int u = 0; u < 2; ++u) {
-    const int q = u == 0 ? wv : NBMAX - 1 - wv;
-    if (q >= NB) continue;
-    double x[NBMAX][4];
-#pragma unroll
-    for (int p = 0; p < NBMAX; ++p)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
-        // clamped address, masked value: every load is issued (the barrier
-        // of the maximum above orders them after all stores of phase R)
-        const double y = gld(&Rg[min(r, K - 1) * K + min(c, K - 1)]);
-        x[p][v] = (p <= q && r < K && c < K) ? y : 0.0;
-      }
-#pragma unroll
-    for (int p = 0; p < NBMAX; ++p) {
-      if (p > q) break;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * p + 4 * v + l4, c = 16 * q + l16;
-        if (r < K && c < K) {
-          const double y = ldexp(x[p][v], -e);
-          gst(&Rg[r * K + c], y);
-          if (rf32) reinterpret_cast<float*>(Rfg)[r * K + c] = (float)y;
-          else reinterpret_cast<double*>(Rfg)[r * K + c] = y;
-        }
+        if (r < K && c < K) gst(&Rig[r * K + c], iacc[q][v]);
       }
     }
   }
