@@ -495,6 +495,15 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
 // is one that no plan still holds behind its head, so the launches of one step
 // are merged whole; each plan's own order is kept, which is all its
 // correctness needs (the problems share no written memory).
+// Node arguments of a merged one-workgroup-per-node launch (Cholesky,
+// eigensolver) ordered by decreasing order K: workgroups start in index
+// order, so the costliest nodes (cost ~ K^3) start first and the launch ends
+// on small ones (longest-processing-time-first).  The nodes of such a launch
+// are independent, so the order changes no result.
+static void sort_largest_first(std::vector<SmallArgs>& v) {
+  std::stable_sort(v.begin(), v.end(), [](const SmallArgs& a, const SmallArgs& b) { return a.K > b.K; });
+}
+
 ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
   const int n = (int)plans.size();
   // steps as integer ids: (kind, label, stream, occurrence in the plan)
@@ -591,8 +600,9 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           // the eigensolver by order: nodes up to 96 run two to a CU
           std::vector<SmallArgs> lo, mid, hi;
           for (const auto& x : sa) (x.K <= 64 ? lo : (x.K <= 96 ? mid : hi)).push_back(x);
-          for (const auto* part : {&lo, &mid, &hi}) {
+          for (auto* part : {&lo, &mid, &hi}) {
             if (part->empty()) continue;
+            sort_largest_first(*part);
             Op e = op;
             e.toff = put(M, *part);
             e.count = (int)part->size();
@@ -607,6 +617,7 @@ ht_status merge_plans(const std::vector<Plan>& plans, Plan& M) {
           }
           break;
         }
+        if (o0.kind == OP_CHOL1 || o0.kind == OP_CHOL2) sort_largest_first(sa);
         op.toff = put(M, sa);
         op.count = (int)sa.size();
         if (o0.kind == OP_RANK) {
