@@ -466,9 +466,21 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
     cls[c].push_back(d);
   }
   constexpr long long kGridMax = 65535;
-  for (const auto& kv : cls) {
-    const auto& v = kv.second;
+  // 128-column items of a streamed product
+  auto sb_items = [](const GemmDesc& d) {
+    const int w = sb_want(d);
+    const long long ns = w == 1 ? d.M : d.N;
+    return (ns + 127) / 128 * (long long)d.nbatch;
+  };
+  for (auto& kv : cls) {
+    auto& v = kv.second;
     const bool tiled = kv.first == kTiled;   // only the tiled kernels put the batch on a grid axis
+    const bool streamed = kv.first >= 10 && kv.first < kTiled;
+    // streamed products of many problems: the largest first (workgroups start
+    // in index order), so that the launch does not end on one big product
+    if (streamed)
+      std::stable_sort(v.begin(), v.end(),
+                       [&](const GemmDesc& a, const GemmDesc& b) { return sb_items(a) > sb_items(b); });
     size_t i = 0;
     while (i < v.size()) {
       std::vector<GemmDesc> chunk;
@@ -480,6 +492,15 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
         chunk.push_back(v[i++]);
       }
       Op op = decide(chunk);
+      if (op.g.sb) {
+        // at least about 2048 workgroups over the launch: with one workgroup
+        // per descriptor a product of 70 items would run on one CU while the
+        // others idle; the surplus workgroups of small products exit at once
+        long long most = 1;
+        for (const auto& d : chunk) most = std::max(most, sb_items(d));
+        const long long per = (2048 + (long long)chunk.size() - 1) / (long long)chunk.size();
+        op.g.sb_grid = (int)std::max<long long>(op.g.sb_grid, std::min(per, most));
+      }
       op.label = proto.label;
       op.stream = proto.stream;
       op.toff = put(P, chunk);
