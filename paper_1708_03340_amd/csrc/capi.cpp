@@ -481,6 +481,12 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
     if (streamed)
       std::stable_sort(v.begin(), v.end(),
                        [&](const GemmDesc& a, const GemmDesc& b) { return sb_items(a) > sb_items(b); });
+    // split-K Grams the same way, by reduction work
+    const bool splitk = kv.first == 2 || kv.first == 3;
+    auto rk_work = [](const GemmDesc& d) { return (double)d.M * d.N * d.K * d.KB; };
+    if (splitk)
+      std::stable_sort(v.begin(), v.end(),
+                       [&](const GemmDesc& a, const GemmDesc& b) { return rk_work(a) > rk_work(b); });
     size_t i = 0;
     while (i < v.size()) {
       std::vector<GemmDesc> chunk;
@@ -500,6 +506,15 @@ void add_gemm_grouped(Plan& P, const std::vector<GemmDesc>& descs, const Op& pro
         for (const auto& d : chunk) most = std::max(most, sb_items(d));
         const long long per = (2048 + (long long)chunk.size() - 1) / (long long)chunk.size();
         op.g.sb_grid = (int)std::max<long long>(op.g.sb_grid, std::min(per, most));
+      }
+      if (op.g.rk) {
+        // likewise for the split-K Grams: at least about 2048 workgroups, each
+        // still at least 16 chunks of 16 deep (a one-workgroup reduction over
+        // 9216 terms had run on one CU)
+        long long chunks = 1;
+        for (const auto& d : chunk) chunks = std::max<long long>(chunks, (long long)((d.K + 15) / 16) * d.KB);
+        const long long per = (2048 + (long long)chunk.size() - 1) / (long long)chunk.size();
+        op.g.rk_split = (int)std::max<long long>(op.g.rk_split, std::min(per, (chunks + 15) / 16));
       }
       op.label = proto.label;
       op.stream = proto.stream;
